@@ -1,0 +1,440 @@
+"""FP64 oracle: ctypes binding of perf_oracle.c plus the solver layer in numpy.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import math
+import os
+import subprocess
+from typing import Callable, Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "perf_oracle.c")
+_LIB = os.path.join(_HERE, "_perf_oracle.so")
+MAX_LAYERS = 8
+
+
+def library_path() -> str:
+    return _LIB
+
+
+def build_oracle(force: bool = True) -> str:
+    """Compile perf_oracle.c with gcc (IEEE double, OpenMP over rays)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Scene(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("bmin", ctypes.c_double * 3), ("bmax", ctypes.c_double * 3),
+        ("n_layers", ctypes.c_int32), ("env_w", ctypes.c_int32), ("env_h", ctypes.c_int32),
+        ("radius", ctypes.c_double * MAX_LAYERS),
+        ("step", ctypes.c_double),
+        ("bg", ctypes.c_double * 3),
+        ("n_cams", ctypes.c_int32), ("width", ctypes.c_int32), ("height", ctypes.c_int32),
+        ("cam_origin", ctypes.c_void_p), ("cam_rot", ctypes.c_void_p), ("cam_intr", ctypes.c_void_p),
+    ]
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build_oracle(force=False)
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        i64 = ctypes.c_int64
+        lib.orc_n_units.restype = i64
+        lib.orc_n_units.argtypes = [P]
+        lib.orc_n_rays.restype = i64
+        lib.orc_n_rays.argtypes = [P]
+        lib.orc_entry_capacity.restype = i64
+        lib.orc_entry_capacity.argtypes = [P]
+        lib.orc_render.argtypes = [P, P, P, P, i64, P, P, P, P]
+        lib.orc_apply_J.argtypes = [P, P, P, P, i64, P]
+        lib.orc_apply_Jt.argtypes = [P, P, P, P, i64, P]
+        lib.orc_apply_JtJ.argtypes = [P, P, P, P, i64, P]
+        lib.orc_grad_blocks.argtypes = [P, P, P, P, i64, P, P, P]
+        lib.orc_footprint.argtypes = [P, P, i64, P, P, P]
+        lib.orc_ray_row.restype = i64
+        lib.orc_ray_row.argtypes = [P, P, i64, ctypes.c_int, i64, P, P, P, P]
+        lib.orc_ray_samples.restype = i64
+        lib.orc_ray_samples.argtypes = [P, P, i64, ctypes.c_int, i64, P, P, P, P, P, P, P, P, P]
+        lib.orc_sample_field.restype = ctypes.c_double
+        lib.orc_sample_field.argtypes = [P, P, P, ctypes.c_int]
+        lib.orc_ray.argtypes = [P, i64, P, P]
+        lib.orc_num_threads.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+class OracleScene:
+    """A scene description (grid, environment layers, cameras) for the oracle."""
+
+    def __init__(self, spec, cams):
+        self.lib = _load()
+        self.spec = spec
+        self.cams = cams
+        if spec.n_layers > MAX_LAYERS:
+            raise ValueError("too many layers")
+        self._origin = _f64(cams.origin).reshape(-1, 3).copy()
+        self._rot = _f64(cams.rot).reshape(-1, 9).copy()
+        self._intr = _f64(np.stack([cams.fx, cams.fy, cams.cx, cams.cy], axis=1)).copy()
+        s = _Scene()
+        s.nx, s.ny, s.nz = spec.nx, spec.ny, spec.nz
+        for i in range(3):
+            s.bmin[i] = spec.bbox_min[i]
+            s.bmax[i] = spec.bbox_max[i]
+            s.bg[i] = spec.background[i]
+        s.n_layers, s.env_w, s.env_h = spec.n_layers, spec.env_w, spec.env_h
+        for i, r in enumerate(spec.layer_radii):
+            s.radius[i] = r
+        s.step = spec.step_vox
+        s.n_cams, s.width, s.height = cams.n, cams.width, cams.height
+        s.cam_origin = self._origin.ctypes.data
+        s.cam_rot = self._rot.ctypes.data
+        s.cam_intr = self._intr.ctypes.data
+        self._s = s
+        self.p = ctypes.addressof(s)
+        self.n_units = int(self.lib.orc_n_units(self.p))
+        self.n_params = 4 * self.n_units
+        self.n_rays = int(self.lib.orc_n_rays(self.p))
+        self.n_vox = spec.n_vox
+
+    # ---------------------------------------------------------------- helpers
+    def _rays(self, rays):
+        if rays is None:
+            return None, self.n_rays
+        r = np.ascontiguousarray(rays, dtype=np.int64)
+        if r.size and (r.min() < 0 or r.max() >= self.n_rays):
+            raise IndexError("ray id out of range")
+        return r, int(r.size)
+
+    def ray(self, ray_id: int):
+        o = np.zeros(3)
+        d = np.zeros(3)
+        self.lib.orc_ray(self.p, int(ray_id), o.ctypes.data, d.ctypes.data)
+        return o, d
+
+    # ---------------------------------------------------------------- operators
+    def render(self, x, targets=None, rays=None):
+        """Eq. 3 per ray: returns (H [n,3], r [n,3] or None, F, T_exit [n])."""
+        x = _f64(x)
+        r_ids, n = self._rays(rays)
+        H = np.zeros((n, 3))
+        Te = np.zeros(n)
+        r = np.zeros((n, 3)) if targets is not None else None
+        t = None if targets is None else np.ascontiguousarray(targets, dtype=np.float32).reshape(-1)
+        F = ctypes.c_double(0.0)
+        self.lib.orc_render(self.p, _ptr(x), _ptr(t), _ptr(r_ids), n, _ptr(H), _ptr(r), ctypes.addressof(F),
+                            _ptr(Te))
+        return H, r, F.value, Te
+
+    def apply_J(self, x, v, rays=None):
+        x, v = _f64(x), _f64(v)
+        r_ids, n = self._rays(rays)
+        u = np.zeros((n, 3))
+        self.lib.orc_apply_J(self.p, _ptr(x), _ptr(v), _ptr(r_ids), n, _ptr(u))
+        return u
+
+    def apply_Jt(self, x, u, rays=None):
+        x, u = _f64(x), _f64(u).reshape(-1)
+        r_ids, n = self._rays(rays)
+        if u.size != 3 * n:
+            raise ValueError("u must have 3 entries per ray")
+        y = np.zeros(self.n_params)
+        self.lib.orc_apply_Jt(self.p, _ptr(x), _ptr(u), _ptr(r_ids), n, _ptr(y))
+        return y
+
+    def apply_JtJ(self, x, v, rays=None):
+        x, v = _f64(x), _f64(v)
+        r_ids, n = self._rays(rays)
+        y = np.zeros(self.n_params)
+        self.lib.orc_apply_JtJ(self.p, _ptr(x), _ptr(v), _ptr(r_ids), n, _ptr(y))
+        return y
+
+    def grad_blocks(self, x, targets, rays=None):
+        """(grad = -J^T r [P], blocks [units,5] = (d, e_r, e_g, e_b, f), F)."""
+        x = _f64(x)
+        t = np.ascontiguousarray(targets, dtype=np.float32).reshape(-1)
+        r_ids, n = self._rays(rays)
+        g = np.zeros(self.n_params)
+        b = np.zeros((self.n_units, 5))
+        F = ctypes.c_double(0.0)
+        self.lib.orc_grad_blocks(self.p, _ptr(x), _ptr(t), _ptr(r_ids), n, _ptr(g), _ptr(b), ctypes.addressof(F))
+        return g, b, F.value
+
+    def footprint(self, rays=None):
+        """(U unique voxels per ray, layers hit per ray, samples per ray)."""
+        r_ids, n = self._rays(rays)
+        U = np.zeros(n, dtype=np.int64)
+        L = np.zeros(n, dtype=np.int32)
+        K = np.zeros(n, dtype=np.int64)
+        self.lib.orc_footprint(self.p, _ptr(r_ids), n, _ptr(U), _ptr(L), _ptr(K))
+        return U, L, K
+
+    def ray_row(self, x, ray_id, mode=0):
+        x = _f64(x)
+        cap = int(self.lib.orc_entry_capacity(self.p))
+        unit = np.zeros(cap, dtype=np.int64)
+        a = np.zeros(cap)
+        s = np.zeros((cap, 3))
+        H = np.zeros(3)
+        m = int(self.lib.orc_ray_row(self.p, _ptr(x), int(ray_id), int(mode), cap, _ptr(unit), _ptr(a), _ptr(s),
+                                     _ptr(H)))
+        return unit[:m].copy(), a[:m].copy(), s[:m].copy(), H
+
+    def ray_samples(self, x, ray_id, mode=0):
+        x = _f64(x)
+        cap = int(self.lib.orc_entry_capacity(self.p))
+        arrs = {k: np.zeros(cap) for k in ("delta", "sigma", "T", "alpha", "dHdc")}
+        c = np.zeros((cap, 3))
+        dHds = np.zeros((cap, 3))
+        H = np.zeros(3)
+        Tend = np.zeros(1)
+        K = int(self.lib.orc_ray_samples(self.p, _ptr(x), int(ray_id), int(mode), cap, _ptr(arrs["delta"]),
+                                         _ptr(arrs["sigma"]), _ptr(arrs["T"]), _ptr(arrs["alpha"]), _ptr(c),
+                                         _ptr(arrs["dHdc"]), _ptr(dHds), _ptr(H), _ptr(Tend)))
+        out = {k: v[:K].copy() for k, v in arrs.items()}
+        out["c"] = c[:K].copy()
+        out["dHds"] = dHds[:K].copy()
+        out["H"] = H
+        out["T_end"] = float(Tend[0])
+        return out
+
+    def sample_field(self, x, p, ch):
+        x = _f64(x)
+        p = _f64(p)
+        return float(self.lib.orc_sample_field(self.p, _ptr(x), _ptr(p), int(ch)))
+
+    def num_threads(self) -> int:
+        return int(self.lib.orc_num_threads())
+
+
+# ------------------------------------------------------------------ preconditioners (Sec. III-G)
+
+def jacobi_diag(blocks: np.ndarray) -> np.ndarray:
+    """diag(J^T J) per parameter from the (d, e, f) blocks: (d, d, d, f) per unit."""
+    b = np.asarray(blocks, dtype=np.float64)
+    return np.stack([b[:, 0], b[:, 0], b[:, 0], b[:, 4]], axis=1).reshape(-1)
+
+
+def jacobi_inverse(blocks: np.ndarray) -> np.ndarray:
+    """M^{-1} = 1/diag(J^T J), 0 where the diagonal is 0."""
+    d = jacobi_diag(blocks)
+    out = np.zeros_like(d)
+    nz = d > 0
+    out[nz] = 1.0 / d[nz]
+    return out
+
+
+def block_matrix(blocks: np.ndarray) -> np.ndarray:
+    """[units,4,4] matrices [[d I, e], [e^T, f]]."""
+    b = np.asarray(blocks, dtype=np.float64)
+    n = b.shape[0]
+    B = np.zeros((n, 4, 4))
+    for i in range(3):
+        B[:, i, i] = b[:, 0]
+        B[:, i, 3] = b[:, 1 + i]
+        B[:, 3, i] = b[:, 1 + i]
+    B[:, 3, 3] = b[:, 4]
+    return B
+
+
+RIDGE = 1e-6
+
+
+def block_inverse(blocks: np.ndarray, ridge: float = RIDGE) -> np.ndarray:
+    """Inverse of each 4x4 block after adding ridge*max(d, f) to the diagonal; 0 for empty units.
+
+    Returned as [units,4,4] (the plain matrix inverse, numpy.linalg.inv).
+    """
+    b = np.asarray(blocks, dtype=np.float64)
+    B = block_matrix(b)
+    m = np.maximum(b[:, 0], b[:, 4])
+    live = m > 0
+    out = np.zeros_like(B)
+    if np.any(live):
+        Bl = B[live] + (ridge * m[live])[:, None, None] * np.eye(4)[None]
+        out[live] = np.linalg.inv(Bl)
+    return out
+
+
+def apply_block_inverse(Binv: np.ndarray, r: np.ndarray) -> np.ndarray:
+    return np.einsum("nij,nj->ni", Binv, np.asarray(r, dtype=np.float64).reshape(-1, 4)).reshape(-1)
+
+
+def apply_precond(kind: str, data, r: np.ndarray) -> np.ndarray:
+    if kind == "none":
+        return np.array(r, dtype=np.float64)
+    if kind == "jacobi":
+        return data * r
+    if kind in ("block", "learned"):
+        return apply_block_inverse(data, r)
+    raise ValueError(kind)
+
+
+# ------------------------------------------------------------------ Alg. 2
+
+@dataclasses.dataclass
+class PCGResult:
+    x: np.ndarray
+    iters: int
+    alpha: list
+    beta: list
+    R: list
+    pAp: list
+    R0: float
+    flags: set
+
+
+def pcg(apply_A: Callable[[np.ndarray], np.ndarray], b: np.ndarray, apply_Minv: Callable[[np.ndarray], np.ndarray],
+        max_iters: int = 20, rel_tol: float = 0.0, abs_eps: float = 0.0, stall_ratio: float = 0.0) -> PCGResult:
+    """Preconditioned conjugate gradient as in Alg. 2, started at x0 = 0.
+
+    Stops after max_iters products with A, when R = r^T r < abs_eps, when
+    sqrt(R / R0) <= rel_tol, or when R / R_prev > stall_ratio (the early exit of
+    Alg. 2; the paper uses 0.85; <= 0 disables it).  A non-positive or
+    non-finite p^T A p stops the iteration before the update ('breakdown').
+    """
+    b = np.asarray(b, dtype=np.float64)
+    x = np.zeros_like(b)
+    r = b.copy()
+    R0 = float(r @ r)
+    R_prev = R0
+    z = apply_Minv(r)
+    p = z.copy()
+    rz = float(r @ z)
+    res = PCGResult(x, 0, [], [], [], [], R0, set())
+    if max_iters <= 0:
+        return res
+    if R0 == 0.0:
+        res.flags.add("converged")
+        return res
+    k = 0
+    while True:
+        Ap = apply_A(p)
+        pAp = float(p @ Ap)
+        res.pAp.append(pAp)
+        if not (pAp > 0.0) or not math.isfinite(pAp):
+            res.flags.add("breakdown")
+            break
+        alpha = rz / pAp
+        x = x + alpha * p
+        r = r - alpha * Ap
+        R = float(r @ r)
+        res.alpha.append(alpha)
+        res.R.append(R)
+        k += 1
+        if abs_eps > 0 and R < abs_eps:
+            res.flags.add("converged")
+            break
+        if rel_tol > 0 and math.sqrt(R / R0) <= rel_tol:
+            res.flags.add("converged")
+            break
+        if stall_ratio > 0 and R / R_prev > stall_ratio:
+            res.flags.add("stall")
+            break
+        if k >= max_iters:
+            break
+        R_prev = R
+        z = apply_Minv(r)
+        rz_new = float(r @ z)
+        beta = rz_new / rz
+        res.beta.append(beta)
+        rz = rz_new
+        p = z + beta * p
+    res.x = x
+    res.iters = k
+    return res
+
+
+# ------------------------------------------------------------------ Alg. 3
+
+def line_search(objective: Callable[[float], float], F0: float, factor: float = 0.7, ls_max: int = 20):
+    """Backtracking of Alg. 3 with a trial cap.
+
+    gamma starts at 1 and shrinks by `factor` while the error keeps falling; at
+    the first strict increase the previous gamma is returned.  With the cap hit,
+    or when no trial beats F0, the trial with the smallest error is returned if
+    it beats F0, else gamma = 0.  Returns (gamma, mu, n_trials, capped).
+    """
+    gamma = 1.0
+    mu_prev = math.inf
+    best_mu, best_gamma = math.inf, 0.0
+    n = 0
+    while n < ls_max:
+        mu = float(objective(gamma))
+        n += 1
+        if mu < best_mu:
+            best_mu, best_gamma = mu, gamma
+        if mu > mu_prev:
+            g = gamma / factor
+            if mu_prev < F0:
+                return g, mu_prev, n, False
+            return 0.0, F0, n, False
+        gamma = factor * gamma
+        mu_prev = mu
+    if best_mu < F0:
+        return best_gamma, best_mu, n, True
+    return 0.0, F0, n, True
+
+
+def project(spec, x: np.ndarray) -> np.ndarray:
+    """sigma >= 0 on voxels, alpha in [0, 1] on texels; colours unconstrained."""
+    y = np.array(x, dtype=np.float64).reshape(-1, 4)
+    nv = spec.n_vox
+    y[:nv, 3] = np.maximum(y[:nv, 3], 0.0)
+    y[nv:, 3] = np.clip(y[nv:, 3], 0.0, 1.0)
+    return y.reshape(-1)
+
+
+def gn_step(scene: OracleScene, x: np.ndarray, targets: np.ndarray, precond: str = "jacobi", max_iters: int = 20,
+            rel_tol: float = 0.0, abs_eps: float = 0.0, stall_ratio: float = 0.0, line_search_on: bool = True,
+            ls_factor: float = 0.7, ls_max: int = 20, learned_minv=None):
+    """One Gauss-Newton step (Eq. 7): b = -J^T r, PCG on J^T J Delta = b, Alg. 3, projected update."""
+    x = np.asarray(x, dtype=np.float64)
+    grad, blocks, F0 = scene.grad_blocks(x, targets)
+    if precond == "jacobi":
+        data = jacobi_inverse(blocks)
+    elif precond == "block":
+        data = block_inverse(blocks)
+    elif precond == "learned":
+        data = learned_minv
+    else:
+        data = None
+    res = pcg(lambda p: scene.apply_JtJ(x, p), grad, lambda r: apply_precond(precond, data, r),
+              max_iters=max_iters, rel_tol=rel_tol, abs_eps=abs_eps, stall_ratio=stall_ratio)
+    delta = res.x
+    spec = scene.spec
+
+    def objective(g):
+        return scene.render(project(spec, x + g * delta), targets)[2]
+
+    if line_search_on:
+        gamma, mu, n_ls, capped = line_search(objective, F0, ls_factor, ls_max)
+    else:
+        gamma, mu, n_ls, capped = 1.0, objective(1.0), 1, False
+    x_new = project(spec, x + gamma * delta)
+    return dict(x=x_new, delta=delta, gamma=gamma, F_before=F0, F_after=mu, pcg=res, blocks=blocks, grad=grad,
+                n_ls=n_ls, ls_capped=capped)

@@ -1,0 +1,497 @@
+"""Pins of the FP64 oracle against facts that do not come from the oracle itself.
+
+Closed forms of the rendering sum (Sec. III-A, Eq. 3-4), the derivative of that
+sum by central finite differences (Sec. III-E), brute-force dense J^T J for the
+matrix-free identity (Eq. 9) and the Jacobi diagonal (Sec. III-G), textbook
+conjugate gradients for Alg. 2, and scripted objectives for Alg. 3.
+"""
+import dataclasses
+import math
+
+import numpy as np
+import pytest
+
+import perf_synth as ps
+
+
+# ----------------------------------------------------------------------------- helpers
+
+def axis_scene(n=8, step=0.5, W=5, H=5, fov=20.0, radii=(1.8,), env=(16, 8), bg=(0.0, 0.0, 0.0)):
+    spec = ps.SceneSpec(n, n, n, layer_radii=radii, env_w=env[0], env_h=env[1], step_vox=step, background=bg)
+    cams = ps.cameras_from_origins([[3.0, 0.0, 0.0]], W, H, fov)
+    return spec, cams
+
+
+def params(spec, grid_rgbs, env_rgba):
+    grid = np.zeros((spec.nz, spec.ny, spec.nx, 4))
+    grid[...] = grid_rgbs
+    env = np.zeros((spec.n_layers, spec.env_h, spec.env_w, 4))
+    env[...] = env_rgba
+    return pack64(grid, env)
+
+
+def pack64(grid, env):
+    return np.concatenate([np.asarray(grid, np.float64).reshape(-1), np.asarray(env, np.float64).reshape(-1)])
+
+
+def random_x(spec, seed, sigma_max=2.0):
+    rng = np.random.default_rng(seed)
+    x = rng.uniform(0.0, 1.0, size=(spec.n_units, 4))
+    x[:spec.n_vox, 3] *= sigma_max
+    return x.reshape(-1)
+
+
+def dense_jacobian_fd(sc, x, rays, eps=1e-6):
+    """Central differences of H (3 per ray) with respect to every parameter."""
+    P = sc.n_params
+    J = np.zeros((3 * len(rays), P))
+    for j in range(P):
+        xp = x.copy(); xp[j] += eps
+        xm = x.copy(); xm[j] -= eps
+        Hp = sc.render(xp, rays=rays)[0].reshape(-1)
+        Hm = sc.render(xm, rays=rays)[0].reshape(-1)
+        J[:, j] = (Hp - Hm) / (2 * eps)
+    return J
+
+
+def dense_jacobian_rows(sc, x, rays, mode=0):
+    P = sc.n_params
+    J = np.zeros((3 * len(rays), P))
+    for i, ray in enumerate(rays):
+        unit, a, s, _ = sc.ray_row(x, ray, mode)
+        for u, aa, ss in zip(unit, a, s):
+            for ch in range(3):
+                J[3 * i + ch, 4 * u + ch] += aa
+                J[3 * i + ch, 4 * u + 3] += ss[ch]
+    return J
+
+
+@pytest.fixture(scope="module")
+def tiny(oracle_mod):
+    w = ps.workload("tiny")
+    spec = dataclasses.replace(w.spec, background=(0.2, 0.3, 0.1))
+    sc = oracle_mod.OracleScene(spec, w.cams)
+    x = random_x(spec, 5)
+    rng = np.random.default_rng(3)
+    U, L, K = sc.footprint()
+    hit = np.nonzero(K > 0)[0]
+    miss = np.nonzero(K == 0)[0]
+    rays = np.concatenate([rng.choice(hit, 28, replace=False), miss[:4]]).astype(np.int64)
+    return sc, spec, x, rays
+
+
+@pytest.fixture(scope="module")
+def tiny_fd(tiny):
+    sc, spec, x, rays = tiny
+    return dense_jacobian_fd(sc, x, rays)
+
+
+# ----------------------------------------------------------------------------- cameras
+
+def test_principal_ray_hits_origin(oracle_mod):
+    w = ps.workload("tiny")  # 13 x 11: the centre pixel sits on the principal point
+    sc = oracle_mod.OracleScene(w.spec, w.cams)
+    for cam in range(w.cams.n):
+        ray = cam * 13 * 11 + 5 * 13 + 6
+        o, d = sc.ray(ray)
+        np.testing.assert_allclose(d, -o / np.linalg.norm(o), atol=1e-14)
+
+
+def test_pinhole_angles(oracle_mod):
+    spec, cams = axis_scene(W=9, H=9, fov=40.0)
+    sc = oracle_mod.OracleScene(spec, cams)
+    f = cams.fx[0]
+    _, d0 = sc.ray(4 * 9 + 4)
+    for k in (1, 2, 4):
+        _, d1 = sc.ray(4 * 9 + 4 + k)   # k pixels to the right
+        _, d2 = sc.ray((4 + k) * 9 + 4)  # k pixels down
+        assert math.isclose(math.acos(np.clip(d0 @ d1, -1, 1)), math.atan(k / f), rel_tol=1e-9)
+        assert math.isclose(math.acos(np.clip(d0 @ d2, -1, 1)), math.atan(k / f), rel_tol=1e-9)
+        # right is +y and down is -z for a camera on +x looking at the origin
+        assert d1[1] > 0 and abs(d1[2]) < 1e-14
+        assert d2[2] < 0 and abs(d2[1]) < 1e-14
+    R = cams.rot[0]
+    np.testing.assert_allclose(R.T @ R, np.eye(3), atol=1e-14)
+
+
+# ----------------------------------------------------------------------------- closed forms of Eq. 3-4
+
+def test_trilinear_reproduces_affine_field(oracle_mod):
+    spec, cams = axis_scene(n=8)
+    sc = oracle_mod.OracleScene(spec, cams)
+    h = 2.0 / 8
+    idx = np.arange(8)
+    cz, cy, cx = np.meshgrid(idx, idx, idx, indexing="ij")
+    centre = lambda i: -1.0 + (i + 0.5) * h
+    field = 0.3 * centre(cx) - 0.7 * centre(cy) + 1.1 * centre(cz) + 0.25
+    grid = np.zeros((8, 8, 8, 4)); grid[..., 3] = field; grid[..., 0] = 2.0
+    x = pack64(grid, np.zeros((1, 8, 16, 4)))
+    rng = np.random.default_rng(0)
+    for _ in range(50):
+        p = rng.uniform(-1 + h / 2, 1 - h / 2, size=3)  # interior: every corner is a real neighbour
+        exp = 0.3 * p[0] - 0.7 * p[1] + 1.1 * p[2] + 0.25
+        assert math.isclose(sc.sample_field(x, p, 3), exp, rel_tol=1e-12, abs_tol=1e-12)
+        assert math.isclose(sc.sample_field(x, rng.uniform(-1, 1, 3), 0), 2.0, rel_tol=1e-14)
+
+
+@pytest.mark.parametrize("step", [0.5, 0.3, 0.7, 1.0])
+def test_uniform_grid_closed_form(oracle_mod, step):
+    """sigma = s0, c = c0 everywhere, one opaque constant layer E:
+    H = c0 (1 - e^{-s0 L}) + e^{-s0 L} E, with L the chord in voxel lengths."""
+    n = 8
+    spec, cams = axis_scene(n=n, step=step, W=5, H=5, fov=10.0)
+    sc = oracle_mod.OracleScene(spec, cams)
+    s0, c0, E = 0.37, np.array([0.2, 0.5, 0.9]), np.array([0.6, 0.1, 0.3])
+    x = params(spec, np.r_[c0, s0], np.r_[E, 1.0])
+    H = sc.render(x)[0]
+    for ray in range(25):
+        py, px = divmod(ray, 5)
+        # ray direction in the camera frame (right=+y, down=-z, forward=-x)
+        dc = np.array([(px + 0.5 - 2.5) / cams.fx[0], (py + 0.5 - 2.5) / cams.fy[0], 1.0])
+        norm = np.linalg.norm(dc)
+        # from (3,0,0) the ray crosses x = +1 and x = -1 inside the box for this narrow FOV
+        chord_world = 2.0 * norm  # x drops by 2 while t grows by 2 * |dc| / dc_z
+        L = chord_world / (2.0 / n)
+        T = math.exp(-s0 * L)
+        np.testing.assert_allclose(H[ray], c0 * (1 - T) + T * E, rtol=1e-12)
+
+
+def test_empty_grid_returns_env_colour(oracle_mod):
+    """sigma = 0 everywhere and one opaque layer whose colour is linear in the
+    texel row: H equals that linear function at the exit direction's polar angle."""
+    spec, cams = axis_scene(n=4, W=7, H=7, fov=40.0, env=(32, 16))
+    sc = oracle_mod.OracleScene(spec, cams)
+    env = np.zeros((1, 16, 32, 4))
+    rows = np.arange(16)[:, None]
+    env[0, :, :, 0] = 0.1 + 0.05 * rows
+    env[0, :, :, 1] = 0.9 - 0.03 * rows
+    env[0, :, :, 2] = 0.5
+    env[0, :, :, 3] = 1.0
+    grid = np.zeros((4, 4, 4, 4)); grid[..., 0:3] = 0.7
+    x = pack64(grid, env)
+    H = sc.render(x)[0]
+    for ray in range(49):
+        o, d = sc.ray(ray)
+        # far intersection with the sphere of radius 1.8 by polynomial roots
+        t = max(np.roots([d @ d, 2 * o @ d, o @ o - 1.8 ** 2]).real)
+        q = (o + t * d) / 1.8
+        v = math.acos(q[2]) / math.pi * 16 - 0.5
+        assert 0.0 <= v <= 15.0
+        np.testing.assert_allclose(H[ray], [0.1 + 0.05 * v, 0.9 - 0.03 * v, 0.5], rtol=1e-12)
+
+
+def test_env_azimuth_linear(oracle_mod):
+    """A layer whose colour is linear in the texel column maps azimuth linearly."""
+    spec, cams = axis_scene(n=4, W=7, H=7, fov=40.0, env=(64, 8))
+    sc = oracle_mod.OracleScene(spec, cams)
+    env = np.zeros((1, 8, 64, 4))
+    env[0, :, :, 0] = 0.01 * np.arange(64)[None, :]
+    env[0, :, :, 3] = 1.0
+    x = pack64(np.zeros((4, 4, 4, 4)), env)
+    H = sc.render(x)[0]
+    for ray in range(49):
+        o, d = sc.ray(ray)
+        t = max(np.roots([d @ d, 2 * o @ d, o @ o - 1.8 ** 2]).real)
+        q = (o + t * d) / 1.8
+        u = (math.atan2(q[1], q[0]) / (2 * math.pi) + 0.5) * 64 - 0.5
+        if 0.0 <= u <= 63.0:  # away from the wrap seam
+            assert math.isclose(H[ray][0], 0.01 * u, rel_tol=1e-11)
+
+
+def test_one_voxel_by_hand(oracle_mod):
+    """A single voxel (index 3 along x) with sigma_j, c_j; a ray along -x through its centre
+    line samples it at offsets -0.75, -0.25, 0.25, 0.75 voxel with weights 1/4, 3/4, 3/4, 1/4."""
+    n = 8
+    spec, cams = axis_scene(n=n, W=1, H=1, fov=10.0, bg=(0.0, 0.0, 0.0))
+    # shift the camera so the principal ray runs along the centre line of voxel row (y=3, z=4)
+    h = 2.0 / n
+    yc, zc = -1 + 3.5 * h, -1 + 4.5 * h
+    cams.origin[0] = [3.0, yc, zc]
+    cams.rot[0] = np.array([[0.0, 0.0, -1.0], [1.0, 0.0, 0.0], [0.0, -1.0, 0.0]])
+    sc = oracle_mod.OracleScene(spec, cams)
+    sig, col = 1.7, np.array([0.3, 0.6, 0.8])
+    grid = np.zeros((n, n, n, 4))
+    grid[4, 3, 4, 0:3] = col
+    grid[4, 3, 4, 3] = sig
+    x = pack64(grid, np.zeros((1, 8, 16, 4)))
+    H = sc.render(x)[0][0]
+    # the ray travels -x: voxel x-index 4 is the 4th voxel from the entry face (x = +1)
+    w = [0.25, 0.75, 0.75, 0.25]
+    T, exp_H = 1.0, np.zeros(3)
+    for wk in w:
+        a = 1 - math.exp(-sig * wk * 0.5)
+        exp_H += T * a * (col * wk)
+        T *= math.exp(-sig * wk * 0.5)
+    np.testing.assert_allclose(H, exp_H, rtol=1e-12)
+
+
+def test_partition_of_unity(oracle_mod):
+    """All colours 1 and background 1: H = sum T_k alpha_k + sum T_l alpha_l + T_end = 1."""
+    w = ps.workload("ragged")
+    spec = dataclasses.replace(w.spec, background=(1.0, 1.0, 1.0))
+    sc = oracle_mod.OracleScene(spec, w.cams)
+    x = random_x(spec, 7, sigma_max=3.0).reshape(-1, 4)
+    x[:, 0:3] = 1.0
+    H = sc.render(x.reshape(-1))[0]
+    np.testing.assert_allclose(H, 1.0, atol=1e-12)
+
+
+def test_transmittance_bounds(oracle_mod, tiny):
+    sc, spec, x, rays = tiny
+    for ray in rays[:10]:
+        s = sc.ray_samples(x, ray)
+        T = np.r_[s["T"], s["T_end"]]
+        assert np.all(T <= 1.0) and np.all(T >= 0.0)
+        assert np.all(np.diff(T) <= 1e-15)
+        if len(s["T"]):
+            assert s["T"][0] == 1.0
+            assert abs(s["delta"].sum() - s["delta"].sum()) == 0.0
+            assert np.all(s["delta"] <= spec.step_vox + 1e-15) and np.all(s["delta"] > 0)
+
+
+def test_axis_ray_footprint(oracle_mod):
+    """Along a grid row through voxel centres every voxel of the row and its
+    +y/+z neighbours is a trilinear corner: U = 4 N."""
+    n = 8
+    spec, cams = axis_scene(n=n, W=1, H=1)
+    h = 2.0 / n
+    cams.origin[0] = [3.0, -1 + 2.5 * h, -1 + 5.5 * h]
+    cams.rot[0] = np.array([[0.0, 0.0, -1.0], [1.0, 0.0, 0.0], [0.0, -1.0, 0.0]])
+    sc = oracle_mod.OracleScene(spec, cams)
+    U, L, K = sc.footprint()
+    assert U[0] == 4 * n and L[0] == 1 and K[0] == 2 * n
+
+
+# ----------------------------------------------------------------------------- derivatives (Sec. III-E)
+
+def test_rows_match_finite_differences(tiny, tiny_fd):
+    sc, spec, x, rays = tiny
+    J = dense_jacobian_rows(sc, x, rays)
+    err = np.abs(J - tiny_fd).max() / np.abs(tiny_fd).max()
+    assert err < 1e-8, err
+
+
+def test_alg1_matches_explicit_partials(tiny):
+    sc, spec, x, rays = tiny
+    for ray in rays:
+        a = sc.ray_samples(x, ray, mode=0)
+        b = sc.ray_samples(x, ray, mode=1)
+        np.testing.assert_allclose(b["dHdc"], a["dHdc"], rtol=1e-12, atol=1e-14)
+        np.testing.assert_allclose(b["dHds"], a["dHds"], rtol=1e-10, atol=1e-13)
+
+
+def test_alg1_without_env_term_is_not_the_derivative(tiny, tiny_fd):
+    """Alg. 1 as printed starts its colour accumulator at zero; with a visible
+    environment that drops a term of dH/dsigma, which finite differences expose."""
+    sc, spec, x, rays = tiny
+    J2 = dense_jacobian_rows(sc, x, rays, mode=2)
+    err = np.abs(J2 - tiny_fd).max() / np.abs(tiny_fd).max()
+    assert err > 1e-3
+
+
+def test_apply_J_matches_dense(tiny, tiny_fd):
+    sc, spec, x, rays = tiny
+    v = np.random.default_rng(1).normal(size=sc.n_params)
+    u = sc.apply_J(x, v, rays=rays).reshape(-1)
+    ref = tiny_fd @ v
+    assert np.linalg.norm(u - ref) / np.linalg.norm(ref) < 1e-8
+
+
+def test_apply_Jt_matches_dense(tiny, tiny_fd):
+    sc, spec, x, rays = tiny
+    u = np.random.default_rng(2).normal(size=3 * len(rays))
+    y = sc.apply_Jt(x, u, rays=rays)
+    ref = tiny_fd.T @ u
+    assert np.linalg.norm(y - ref) / np.linalg.norm(ref) < 1e-8
+
+
+def test_adjoint_identity(tiny):
+    sc, spec, x, rays = tiny
+    rng = np.random.default_rng(4)
+    v = rng.normal(size=sc.n_params)
+    u = rng.normal(size=3 * len(rays))
+    Jv = sc.apply_J(x, v, rays=rays).reshape(-1)
+    Jtu = sc.apply_Jt(x, u, rays=rays)
+    assert abs(u @ Jv - Jtu @ v) <= 1e-12 * np.linalg.norm(u) * np.linalg.norm(Jv) * 10
+
+
+def test_JtJ_matches_dense(tiny, tiny_fd):
+    sc, spec, x, rays = tiny
+    v = np.random.default_rng(5).normal(size=sc.n_params)
+    y = sc.apply_JtJ(x, v, rays=rays)
+    ref = tiny_fd.T @ (tiny_fd @ v)
+    assert np.linalg.norm(y - ref) / np.linalg.norm(ref) < 1e-8
+    w = np.random.default_rng(6).normal(size=sc.n_params)
+    Jv = sc.apply_J(x, v, rays=rays).reshape(-1)
+    Jw = sc.apply_J(x, w, rays=rays).reshape(-1)
+    assert math.isclose(w @ y, Jw @ Jv, rel_tol=1e-10)
+    assert v @ y >= 0
+
+
+def test_blocks_match_dense_JtJ(tiny, tiny_fd):
+    sc, spec, x, rays = tiny
+    targets = np.zeros((sc.n_rays, 3), np.float32)
+    grad, blocks, F = sc.grad_blocks(x, targets, rays=rays)
+    A = tiny_fd.T @ tiny_fd
+    scale = np.abs(A).max()
+    for unit in range(sc.n_units):
+        Bd = A[4 * unit:4 * unit + 4, 4 * unit:4 * unit + 4]
+        b = blocks[unit]
+        exp = np.array([[b[0], 0, 0, b[1]], [0, b[0], 0, b[2]], [0, 0, b[0], b[3]], [b[1], b[2], b[3], b[4]]])
+        assert np.abs(Bd - exp).max() <= 1e-8 * scale
+    diag = np.diag(A)
+    np.testing.assert_allclose(_oracle().jacobi_diag(blocks), diag, atol=1e-8 * scale)
+
+
+def _oracle():
+    import oracle
+    return oracle
+
+
+def test_gradient_matches_fd_of_objective(tiny, tiny_fd):
+    sc, spec, x, rays = tiny
+    rng = np.random.default_rng(8)
+    targets = rng.uniform(0, 1, size=(sc.n_rays, 3)).astype(np.float32)
+    grad, blocks, F = sc.grad_blocks(x, targets, rays=rays)
+    H = sc.render(x, rays=rays)[0]
+    r = (H - targets[rays].astype(np.float64)).reshape(-1)
+    assert math.isclose(F, 0.5 * r @ r, rel_tol=1e-12)
+    ref = -(tiny_fd.T @ r)
+    assert np.linalg.norm(grad - ref) / np.linalg.norm(ref) < 1e-8
+    # and directly: central differences of F along a random direction
+    v = rng.normal(size=sc.n_params)
+    eps = 1e-6
+    Fp = sc.render(x + eps * v, targets, rays=rays)[2]
+    Fm = sc.render(x - eps * v, targets, rays=rays)[2]
+    assert math.isclose((Fp - Fm) / (2 * eps), -(grad @ v), rel_tol=1e-6)
+
+
+# ----------------------------------------------------------------------------- preconditioner inverse
+
+def test_block_inverse_is_inverse(oracle_mod):
+    rng = np.random.default_rng(9)
+    n = 200
+    e = rng.normal(size=(n, 3))
+    d = rng.uniform(0.5, 2.0, n)
+    f = (e * e).sum(1) / d + rng.uniform(0.1, 1.0, n)  # SPD: f > e.e / d
+    blocks = np.stack([d, e[:, 0], e[:, 1], e[:, 2], f], axis=1)
+    blocks[:5] = 0.0  # empty units
+    Binv = oracle_mod.block_inverse(blocks, ridge=0.0)
+    B = oracle_mod.block_matrix(blocks)
+    for i in range(5, n):
+        np.testing.assert_allclose(B[i] @ Binv[i], np.eye(4), atol=1e-10)
+    assert np.all(Binv[:5] == 0)
+    jac = oracle_mod.jacobi_inverse(blocks)
+    assert np.all(jac[:20] == 0)
+    np.testing.assert_allclose(jac[20:24], [1 / d[5]] * 3 + [1 / f[5]])
+
+
+# ----------------------------------------------------------------------------- Alg. 2
+
+def _spd(n, rank, seed):
+    rng = np.random.default_rng(seed)
+    J = rng.normal(size=(max(rank, 1), n))
+    return J.T @ J, rng.normal(size=n)
+
+
+def test_pcg_solves_spd_system(oracle_mod):
+    A, b = _spd(12, 30, 0)
+    for minv in (np.ones(12), 1.0 / np.diag(A)):
+        res = oracle_mod.pcg(lambda p: A @ p, b, lambda r: minv * r, max_iters=40, abs_eps=1e-28)
+        np.testing.assert_allclose(res.x, np.linalg.solve(A, b), rtol=1e-8, atol=1e-10)
+
+
+def test_pcg_singular_gives_min_norm(oracle_mod):
+    A, _ = _spd(12, 5, 1)
+    b = A @ np.random.default_rng(2).normal(size=12)  # consistent right-hand side in range(A)
+    res = oracle_mod.pcg(lambda p: A @ p, b, lambda r: r, max_iters=30, abs_eps=1e-26)
+    np.testing.assert_allclose(res.x, np.linalg.lstsq(A, b, rcond=None)[0], rtol=1e-6, atol=1e-8)
+
+
+def test_pcg_direction_conjugacy(oracle_mod):
+    A, b = _spd(10, 40, 3)
+    dirs = []
+    minv = 1.0 / np.diag(A)
+
+    def rec(p):
+        dirs.append(p.copy())
+        return A @ p
+
+    oracle_mod.pcg(rec, b, lambda r: minv * r, max_iters=6)
+    for i in range(len(dirs)):
+        for j in range(i):
+            assert abs(dirs[i] @ A @ dirs[j]) <= 1e-9 * math.sqrt((dirs[i] @ A @ dirs[i]) * (dirs[j] @ A @ dirs[j]))
+
+
+def test_pcg_stopping_rules(oracle_mod):
+    A, b = _spd(30, 60, 4)
+    res = oracle_mod.pcg(lambda p: A @ p, b, lambda r: r, max_iters=7)
+    assert res.iters == 7 and len(res.alpha) == 7 and len(res.beta) == 6
+    res = oracle_mod.pcg(lambda p: A @ p, b, lambda r: r, max_iters=100, rel_tol=1e-3)
+    assert math.sqrt(res.R[-1] / res.R0) <= 1e-3 and math.sqrt(res.R[-2] / res.R0) > 1e-3
+    res = oracle_mod.pcg(lambda p: -(A @ p), b, lambda r: r, max_iters=5)
+    assert "breakdown" in res.flags and res.iters == 0 and np.all(res.x == 0)
+    res = oracle_mod.pcg(lambda p: A @ p, np.zeros(30), lambda r: r, max_iters=5)
+    assert "converged" in res.flags and res.iters == 0
+
+
+# ----------------------------------------------------------------------------- Alg. 3
+
+def test_line_search_scripted(oracle_mod):
+    calls = []
+
+    def quad(g):
+        calls.append(g)
+        return (g - 0.3) ** 2
+
+    g, mu, n, capped = oracle_mod.line_search(quad, F0=1.0)
+    # errors at 1, .7, .49, .343, .2401: the last is the first increase, so .343 comes back
+    assert math.isclose(g, 0.343, rel_tol=1e-12) and n == 5 and not capped
+    assert math.isclose(mu, (0.343 - 0.3) ** 2, rel_tol=1e-12)
+    # never increasing: the cap ends it and the smallest error wins
+    g, mu, n, capped = oracle_mod.line_search(lambda g: g, F0=10.0, ls_max=6)
+    assert capped and n == 6 and math.isclose(g, 0.7 ** 5)
+    # no trial beats the current error: no step
+    g, mu, n, capped = oracle_mod.line_search(lambda g: 5.0 + (g - 0.5) ** 2, F0=1.0)
+    assert g == 0.0 and mu == 1.0
+    # ties keep shrinking (strict comparison)
+    seq = iter([3.0, 3.0, 2.0, 2.5])
+    g, mu, n, capped = oracle_mod.line_search(lambda g: next(seq), F0=4.0)
+    assert math.isclose(g, 0.49) and mu == 2.0
+
+
+# ----------------------------------------------------------------------------- Gauss-Newton (Eq. 7)
+
+def _observed_problem(oracle_mod, n=4, seed=21):
+    spec = ps.SceneSpec(n, n, n, layer_radii=(1.8,), env_w=8, env_h=4)
+    rng = np.random.default_rng(seed)
+    cams = ps.make_cameras("sphere", 12, 12, 12, 50.0, 3.0, rng)
+    sc = oracle_mod.OracleScene(spec, cams)
+    x_gt = random_x(spec, seed + 1, sigma_max=1.0)
+    x_gt.reshape(-1, 4)[spec.n_vox:, 3] = 0.8
+    targets = sc.render(x_gt)[0].astype(np.float32)
+    return spec, sc, x_gt, targets
+
+
+def test_zero_residual_fixed_point(oracle_mod):
+    spec, sc, x_gt, targets = _observed_problem(oracle_mod)
+    xg = x_gt.astype(np.float32).astype(np.float64)
+    out = oracle_mod.gn_step(sc, xg, sc.render(xg)[0].astype(np.float32).astype(np.float64), max_iters=5)
+    # targets equal to the render up to float32 rounding: tiny gradient and a tiny step
+    assert out["F_before"] < 1e-12
+    assert np.abs(out["x"] - xg).max() < 1e-5
+
+
+def test_gauss_newton_converges_near_ground_truth(oracle_mod):
+    spec, sc, x_gt, targets = _observed_problem(oracle_mod)
+    rng = np.random.default_rng(0)
+    x = x_gt + 0.02 * rng.normal(size=x_gt.size)
+    x = oracle_mod.project(spec, x)
+    Fs = []
+    for _ in range(4):
+        out = oracle_mod.gn_step(sc, x, targets, precond="jacobi", max_iters=200, rel_tol=1e-10)
+        Fs.append(out["F_before"])
+        assert out["F_after"] <= out["F_before"]
+        x = out["x"]
+    Fs.append(sc.render(x, targets)[2])
+    assert Fs[-1] < 1e-6 * Fs[0], Fs
