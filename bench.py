@@ -1,0 +1,171 @@
+"""Benchmark: Gauss-Newton steps (PCG with J^T J v) on one MI355X.
+
+One step = one Gauss-Newton step of the whole path: the gradient and exact 4x4 blocks
+of J^T J in one traversal, the preconditioner, PCG (30 products J^T J v), the
+backtracking line search (full renders of the objective) and the projected update.
+
+Workload: the 128^3 object-in-a-box scene (40 seeded spheres/boxes, 3 environment
+layers of 256x128 at radii 1.8/3/6, 100 cameras of 400x400 on the upper hemisphere at
+radius 4: 16 M rays).  Targets are rendered by the library from the ground-truth
+parameters; the solve starts from grey colour 0.5, opacity 0.01.
+
+value = rays pushed through J^T J v per second of whole-step wall time (every other
+part of the step counts as overhead).  The roofline object prices the J^T J v kernel
+alone: footprint bytes per launch (48 B per distinct voxel a ray touches + 192 B per
+environment layer it hits, counted exactly by the library's footprint pass) over the
+kernel's average duration measured with HIP events on the launch stream.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "jtj_cfg2_traffic.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2112_05598_amd", "csrc", "raymarch.hip")
+
+
+def kernel_sha() -> str:
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic(n_jtj_units: float):
+    """HBM bytes per J^T J v launch from committed rocprofv3 counters, if they were taken on
+    the current kernel source; None otherwise."""
+    try:
+        rec = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_sha") != kernel_sha():
+        return None
+    return rec.get("bytes_per_dispatch")
+
+
+def cpu_baseline(w, max_seconds: float = 20.0):
+    """The FP64 oracle's J^T J v on a strided sample of the same rays, on the host cores."""
+    import numpy as np
+    import oracle
+    orc = oracle.OracleScene(w.spec, w.cams)
+    v = np.random.default_rng(7).normal(size=orc.n_params)
+    x = w.x_init.astype(np.float64)
+    # calibrate on a small sample, then size the timed sample to ~max_seconds
+    probe = np.arange(0, orc.n_rays, max(orc.n_rays // 4096, 1), dtype=np.int64)
+    t0 = time.perf_counter()
+    orc.apply_JtJ(x, v, rays=probe)
+    per_ray = (time.perf_counter() - t0) / len(probe)
+    n = int(min(orc.n_rays, max(4096, max_seconds / max(per_ray, 1e-9))))
+    stride = max(orc.n_rays // n, 1)
+    sample = np.arange(0, orc.n_rays, stride, dtype=np.int64)
+    t0 = time.perf_counter()
+    orc.apply_JtJ(x, v, rays=sample)
+    dt = time.perf_counter() - t0
+    return {"value": len(sample) / dt, "unit": "rays/s", "cores": orc.num_threads(), "kind": "oracle",
+            "sample": f"J^T J v over every {stride}-th ray ({len(sample)} of {orc.n_rays} rays), FP64, "
+                      f"{dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="cfg2")
+    ap.add_argument("--pcg", type=int, default=30)
+    ap.add_argument("--precond", default="jacobi")
+    ap.add_argument("--dtype", default="f32", choices=["f32", "bf16"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (the ray-sharded design is "
+              "described, not built); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import perf_synth as ps
+    from paper_2112_05598_amd.scene import Scene
+
+    dev = torch.device("cuda:0")
+    w = ps.workload(args.workload)
+    print(f"[bench] workload {w.name}: grid {w.spec.nx}^3, {w.spec.n_layers} layers {w.spec.env_w}x{w.spec.env_h}, "
+          f"{w.cams.n} cams {w.cams.width}x{w.cams.height}, P={w.spec.n_params}", file=sys.stderr, flush=True)
+    sc = Scene(w.spec, w.cams, None, param_dtype="f32", device="cuda:0")
+    x_gt = torch.from_numpy(w.x_gt).to(dev)
+    H, _ = sc.render_residuals(x_gt)           # no targets yet: the render itself
+    targets = H.clone()
+    sc.set_targets(targets)
+    if args.dtype == "bf16":
+        sc = Scene(w.spec, w.cams, targets, param_dtype="bf16", device="cuda:0")
+    _, tot = sc.footprint(per_ray=False)
+    tot = tot.cpu().numpy()
+    bytes_per_launch = 48.0 * float(tot[0]) + 192.0 * float(tot[1])
+
+    x0 = torch.from_numpy(w.x_init).to(dev)
+    opts = dict(max_iters=args.pcg, precond=args.precond)
+    xw = x0.clone()
+    for i in range(args.warmup):
+        sc.gn_step(xw, **opts)
+        print(f"[bench] warmup step {i} done", file=sys.stderr, flush=True)
+    x = x0.clone()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = []
+    for i in range(args.steps):
+        st = sc.gn_step(x, **opts)
+        stats.append(st)
+        print(f"[bench] step {i}: F {st['F_before']:.6g} -> {st['F_after']:.6g} gamma {st['gamma']:.3g} "
+              f"pcg {st['pcg_iters']} ls {st['ls_trials']} {st['ms_phase'][5]:.1f} ms "
+              f"(jtj {st['ms_jtj'] / max(st['n_jtj'], 1):.2f} ms avg)", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+
+    n_jtj = sum(s["n_jtj"] for s in stats)
+    jtj_ms = sum(s["ms_jtj"] for s in stats) / max(n_jtj, 1)
+    value = sc.n_rays * n_jtj / dt
+    achieved = bytes_per_launch / (jtj_ms * 1e-3) / 1e9
+    traffic = measured_traffic(n_jtj)
+    out = {
+        "metric": "J^T J.v rays/s (% HBM roofline); GN time-to-residual, learned vs Jacobi PCG",
+        "value": value,
+        "unit": "rays/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.dtype,
+        "data": "synthetic",
+        "config": {"workload": f"{w.name}: {w.spec.nx}^3 RGB-sigma grid, {w.spec.n_layers} env layers "
+                               f"{w.spec.env_w}x{w.spec.env_h} at radii {list(w.spec.layer_radii)}, {w.cams.n} cams "
+                               f"{w.cams.width}x{w.cams.height} on the upper hemisphere r=4, 40 random spheres/boxes",
+                   "rays": sc.n_rays, "params": sc.n_params, "pcg_iters_per_step": args.pcg,
+                   "precond": args.precond, "step_vox": w.spec.step_vox},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "k_ray<M_JTJ> (J^T J v)", "avg_launch_ms": jtj_ms,
+                     "bytes_per_launch": bytes_per_launch, "launches": n_jtj,
+                     "kernel_rays_per_s": sc.n_rays / (jtj_ms * 1e-3)},
+        "gn": {"F": [stats[0]["F_before"]] + [s["F_after"] for s in stats],
+               "ms_per_gn_step": [s["ms_phase"][5] for s in stats],
+               "pcg_iters": [s["pcg_iters"] for s in stats], "gamma": [s["gamma"] for s in stats]},
+        "footprint": {"sum_U": int(tot[0]), "layer_hits": int(tot[1]), "rays_in_grid": int(tot[2])},
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle on a ray sample", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,193 @@
+"""Python handle over the C ABI: device memory and streams come from PyTorch,
+every step of the computation runs in libperf_gn.so."""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import abi
+
+_PRECOND = {"none": abi.PERF_PRECOND_NONE, "jacobi": abi.PERF_PRECOND_JACOBI, "block": abi.PERF_PRECOND_BLOCK4,
+            "learned": abi.PERF_PRECOND_LEARNED}
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def make_desc(spec, width: int, height: int, param_dtype: str = "f32", checks: bool = False,
+              learned: bool = False) -> abi.perf_scene_desc:
+    d = abi.perf_scene_desc()
+    d.nx, d.ny, d.nz = spec.nx, spec.ny, spec.nz
+    for i in range(3):
+        d.bbox_min[i] = spec.bbox_min[i]
+        d.bbox_max[i] = spec.bbox_max[i]
+        d.background[i] = spec.background[i]
+    d.n_layers = len(spec.layer_radii)
+    d.env_w, d.env_h = spec.env_w, spec.env_h
+    for i, r in enumerate(spec.layer_radii):
+        d.layer_radius[i] = r
+    d.step_vox = spec.step_vox
+    d.param_dtype = abi.PERF_BF16 if param_dtype == "bf16" else abi.PERF_F32
+    d.width, d.height = width, height
+    d.checks = 1 if checks else 0
+    d.learned = 1 if learned else 0
+    return d
+
+
+def make_cameras(cams) -> ctypes.Array:
+    arr = (abi.perf_camera * cams.n)()
+    for c in range(cams.n):
+        for i in range(3):
+            arr[c].origin[i] = float(cams.origin[c][i])
+        rot = np.asarray(cams.rot[c], dtype=np.float64).reshape(3, 3)
+        for i in range(9):
+            arr[c].rot[i] = float(rot.reshape(-1)[i])
+        arr[c].fx, arr[c].fy = float(cams.fx[c]), float(cams.fy[c])
+        arr[c].cx, arr[c].cy = float(cams.cx[c]), float(cams.cy[c])
+    return arr
+
+
+class Scene:
+    """A grid + environment layers + posed images living on one GPU."""
+
+    def __init__(self, spec, cams, targets: Optional[torch.Tensor] = None, param_dtype: str = "f32",
+                 checks: bool = False, learned: bool = False, device: str = "cuda"):
+        self.lib = abi.load()
+        self.spec = spec
+        self.device = torch.device(device)
+        self.param_dtype = param_dtype
+        self.desc = make_desc(spec, cams.width, cams.height, param_dtype, checks, learned)
+        self._cams = make_cameras(cams)
+        n = cams.n
+        nbytes = int(self.lib.perf_workspace_bytes(ctypes.byref(self.desc), n))
+        if nbytes == 0:
+            abi.check(abi.PERF_EINVAL)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        self._ws_ptr = (base + 255) & ~255
+        self._ws_bytes = nbytes
+        self._targets = targets
+        h = ctypes.c_void_p()
+        abi.check(self.lib.perf_init_scene(ctypes.byref(self.desc), self._cams, n, _ptr(targets),
+                                           ctypes.c_void_p(self._ws_ptr), nbytes, self._stream(), ctypes.byref(h)))
+        self.handle = h
+        nr, nu, npar = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        abi.check(self.lib.perf_scene_sizes(h, ctypes.byref(nr), ctypes.byref(nu), ctypes.byref(npar)))
+        self.n_rays, self.n_units, self.n_params = nr.value, nu.value, npar.value
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            self.lib.perf_destroy_scene(h)
+            self.handle = None
+
+    # ------------------------------------------------------------ plumbing
+    def _stream(self):
+        return ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
+
+    def _bind(self):
+        abi.check(self.lib.perf_set_stream(self.handle, self._stream()))
+
+    def _check_params(self, x: torch.Tensor):
+        want = torch.float32 if self.param_dtype == "f32" else torch.bfloat16
+        if x.dtype != want or x.numel() != self.n_params or not x.is_contiguous() or x.device != self.device:
+            raise ValueError(f"parameters must be a contiguous {self.n_params}-element {want} tensor on {self.device}")
+
+    def _vec(self, t: torch.Tensor, n: int, name: str):
+        if t.dtype != torch.float32 or t.numel() != n or not t.is_contiguous() or t.device != self.device:
+            raise ValueError(f"{name} must be a contiguous float32 tensor of {n} elements on {self.device}")
+
+    def set_targets(self, targets: torch.Tensor):
+        self._vec(targets, 3 * self.n_rays, "targets")
+        self._targets = targets
+        abi.check(self.lib.perf_set_targets(self.handle, _ptr(targets)))
+
+    def pack_bf16(self, x: torch.Tensor) -> torch.Tensor:
+        self._vec(x, x.numel(), "x")
+        out = torch.empty(x.numel(), dtype=torch.bfloat16, device=self.device)
+        abi.check(self.lib.perf_pack_bf16(_ptr(x), _ptr(out), x.numel(), self._stream()))
+        return out
+
+    # ------------------------------------------------------------ operators
+    def render_residuals(self, x: torch.Tensor, want_r: bool = True):
+        self._check_params(x)
+        self._bind()
+        r = torch.empty(self.n_rays * 3, dtype=torch.float32, device=self.device) if want_r else None
+        F = torch.zeros(1, dtype=torch.float64, device=self.device)
+        abi.check(self.lib.perf_render_residuals(self.handle, _ptr(x), _ptr(r), _ptr(F)))
+        return r, F
+
+    def apply_J(self, x, v, out=None):
+        self._check_params(x)
+        self._vec(v, self.n_params, "v")
+        self._bind()
+        u = out if out is not None else torch.empty(self.n_rays * 3, dtype=torch.float32, device=self.device)
+        abi.check(self.lib.perf_apply_J(self.handle, _ptr(x), _ptr(v), _ptr(u)))
+        return u
+
+    def apply_Jt(self, x, u, out=None):
+        self._check_params(x)
+        self._vec(u, 3 * self.n_rays, "u")
+        self._bind()
+        y = out if out is not None else torch.empty(self.n_params, dtype=torch.float32, device=self.device)
+        abi.check(self.lib.perf_apply_Jt(self.handle, _ptr(x), _ptr(u), _ptr(y)))
+        return y
+
+    def apply_JtJ(self, x, v, out=None):
+        self._check_params(x)
+        self._vec(v, self.n_params, "v")
+        self._bind()
+        y = out if out is not None else torch.empty(self.n_params, dtype=torch.float32, device=self.device)
+        abi.check(self.lib.perf_apply_JtJ(self.handle, _ptr(x), _ptr(v), _ptr(y)))
+        return y
+
+    def build_precond(self, x, kind: str = "jacobi"):
+        """(grad = -J^T r [P], blocks [units,5], M^-1 ([P] Jacobi or [units,10] block), F)."""
+        self._check_params(x)
+        self._bind()
+        k = _PRECOND[kind]
+        grad = torch.empty(self.n_params, dtype=torch.float32, device=self.device)
+        blocks = torch.empty(self.n_units * 5, dtype=torch.float32, device=self.device)
+        out = None
+        if k == abi.PERF_PRECOND_JACOBI:
+            out = torch.empty(self.n_params, dtype=torch.float32, device=self.device)
+        elif k == abi.PERF_PRECOND_BLOCK4:
+            out = torch.empty(self.n_units * 10, dtype=torch.float32, device=self.device)
+        F = torch.zeros(1, dtype=torch.float64, device=self.device)
+        abi.check(self.lib.perf_build_precond(self.handle, _ptr(x), k, _ptr(grad), _ptr(blocks), _ptr(out), _ptr(F)))
+        return grad, blocks.view(-1, 5), out, F
+
+    def objective(self, x, delta=None, gamma: float = 1.0) -> float:
+        self._vec(x, self.n_params, "x")
+        self._bind()
+        F = ctypes.c_double()
+        abi.check(self.lib.perf_objective(self.handle, _ptr(x), _ptr(delta), ctypes.c_float(gamma), ctypes.byref(F)))
+        return F.value
+
+    def footprint(self, per_ray: bool = True):
+        self._bind()
+        pr = torch.empty(self.n_rays * 2, dtype=torch.int32, device=self.device) if per_ray else None
+        tot = torch.zeros(3, dtype=torch.int64, device=self.device)
+        abi.check(self.lib.perf_footprint(self.handle, _ptr(pr), _ptr(tot)))
+        return (pr.view(-1, 2) if pr is not None else None), tot
+
+    def gn_step(self, x: torch.Tensor, max_iters: int = 20, precond: str = "jacobi", rel_tol: float = 0.0,
+                abs_eps: float = 0.0, stall_ratio: float = 0.0, line_search: bool = True, ls_factor: float = 0.7,
+                ls_max: int = 20) -> dict:
+        self._vec(x, self.n_params, "x")
+        self._bind()
+        o = abi.perf_pcg_opts()
+        o.max_iters, o.rel_tol, o.abs_eps, o.stall_ratio = max_iters, rel_tol, abs_eps, stall_ratio
+        o.precond = _PRECOND[precond]
+        o.line_search = 1 if line_search else 0
+        o.ls_factor, o.ls_max = ls_factor, ls_max
+        st = abi.perf_gn_stats()
+        abi.check(self.lib.perf_gn_step(self.handle, _ptr(x), ctypes.byref(o), ctypes.byref(st)))
+        k = st.pcg_iters
+        return dict(F_before=st.F_before, F_after=st.F_after, gamma=st.gamma, pcg_iters=k, ls_trials=st.ls_trials,
+                    flags=st.flags, R0=st.R0, R=list(st.R[:k]), alpha=list(st.alpha[:k]),
+                    beta=list(st.beta[:max(k - 1, 0)]), pAp=list(st.pAp[:k + 1]), ms_phase=list(st.ms_phase[:6]), ms_jtj=st.ms_phase[6], n_jtj=int(st.ms_phase[7]))
