@@ -101,8 +101,8 @@ Geo make_geo(const perf_scene_desc& d, int n_cams) {
     g.width = d.width;
     g.height = d.height;
     g.n_cams = n_cams;
-    g.tiles_x = (d.width + kTile - 1) / kTile;
-    g.tiles_y = (d.height + kTile - 1) / kTile;
+    g.tiles_x = (d.width + kTileX - 1) / kTileX;
+    g.tiles_y = (d.height + kTileY - 1) / kTileY;
     g.n_tiles = g.tiles_x * g.tiles_y;
     const int n[3] = {d.nx, d.ny, d.nz};
     float h = INFINITY;

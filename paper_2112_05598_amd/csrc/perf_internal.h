@@ -9,8 +9,10 @@
 namespace perf {
 
 constexpr int kMaxLayers = PERF_MAX_LAYERS;
-constexpr int kBlock = 256;     // threads per ray workgroup: 4 wave64, 16x16 pixel tile
-constexpr int kTile = 16;       // pixels per tile side; each wave owns an 8x8 quarter
+constexpr int kWaves = 2;       // wave64s per ray workgroup
+constexpr int kBlock = 64 * kWaves;
+constexpr int kTileX = 16;      // ray workgroup tile: 16 x 8 pixels, each wave an 8x8 half
+constexpr int kTileY = 8;
 constexpr int kVecBlock = 256;  // threads per vector workgroup
 constexpr int kVecGrid = 2048;  // workgroups of the grid-stride vector kernels (FP64 partials)
 

@@ -1,8 +1,9 @@
 // Per-ray kernels of the Gauss-Newton step on gfx950.
 //
-// One lane marches one pixel ray; a 256-thread workgroup owns a 16x16 pixel tile of one
-// camera and each wave64 an 8x8 quarter of it, so the lanes of a wave sample neighbouring
-// rays at the same step index and their trilinear gathers hit the same cache lines.
+// One lane marches one pixel ray; a 128-thread workgroup owns a 16x8 pixel tile of one
+// camera and each wave64 an 8x8 half of it.  The lanes of a wave march their rays in step
+// at matched depths, so their trilinear gathers hit the same cache lines and their
+// scatter lands in one small voxel window that the wave combines in LDS before HBM.
 //
 // Per ray (Sec. III-A, Eq. 3-4): slab test against the grid box, K = ceil(L / step)
 // samples at the midpoints of equal steps of `step` voxel lengths (the last one shortened
@@ -114,8 +115,14 @@ __device__ __forceinline__ float sample_at(const Geo& G, const Ray& r, int k, fl
 struct Corners {
     int v;          // lower corner voxel
     int i[3];       // lower corner coordinates
+    float f[3];     // fractional position inside the cell
     float w[8];     // weights, corner j = (j&1, j>>1&1, j>>2) offsets
 };
+
+__device__ __forceinline__ float corner_weight(const Corners& c, int j) {
+    return ((j & 1) ? c.f[0] : 1.0f - c.f[0]) * ((j & 2) ? c.f[1] : 1.0f - c.f[1]) *
+           ((j & 4) ? c.f[2] : 1.0f - c.f[2]);
+}
 
 __device__ __forceinline__ void corners(const Geo& G, const float g[3], Corners& c) {
     const int n[3] = {G.nx, G.ny, G.nz};
@@ -126,6 +133,7 @@ __device__ __forceinline__ void corners(const Geo& G, const float g[3], Corners&
         const int i0 = min((int)gc, n[a] - 2);
         c.i[a] = i0;
         f[a] = gc - (float)i0;
+        c.f[a] = f[a];
     }
     c.v = (c.i[2] * G.ny + c.i[1]) * G.nx + c.i[0];
     const float wx0 = 1.0f - f[0], wx1 = f[0];
@@ -185,6 +193,311 @@ __device__ __forceinline__ bool env_hit(const Geo& G, const Ray& r, int l, float
 
 __device__ __forceinline__ void atomic_add(float* p, float v) { unsafeAtomicAdd(p, v); }
 
+// ------------------------------------------------------------------ wave helpers
+__device__ __forceinline__ int wave_min_i(int v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = min(v, __shfl_xor(v, off, 64));
+    return v;
+}
+__device__ __forceinline__ int wave_max_i(int v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = max(v, __shfl_xor(v, off, 64));
+    return v;
+}
+__device__ __forceinline__ float wave_min_f(float v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = fminf(v, __shfl_xor(v, off, 64));
+    return v;
+}
+__device__ __forceinline__ float wave_max_f(float v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+    return v;
+}
+__device__ __forceinline__ bool wave_any(bool b) { return __ballot(b) != 0ull; }
+__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+
+__device__ __forceinline__ void lds_add(__attribute__((address_space(3))) float* p, float v) {
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+}
+__device__ __forceinline__ float lds_take(__attribute__((address_space(3))) float* p) {
+    return __hip_atomic_exchange(p, 0.0f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+}
+
+// ------------------------------------------------------------------ per-wave scatter combining
+// An 8x8x8 voxel window held in LDS as a ring buffer (voxel (x,y,z) lives in slot
+// (x&7, y&7, z&7)), one window per wave.  The lanes of a wave march neighbouring rays at
+// matched depths, so every step's trilinear corners fall inside the window and are added
+// there; when the wave moves on, the voxels that leave the window are flushed to HBM with
+// one global atomic per channel (non-zero voxels only) and their slots cleared.  Each voxel
+// a wave touches then costs one flush instead of one global atomic per sample, corner and
+// ray.  Lanes whose corners do not fit go straight to global atomics.
+constexpr int kB = 8;
+constexpr int kB3 = kB * kB * kB;
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+// explicit LDS pointers, so accesses compile to ds_* instructions rather than flat ones
+#define LDS __attribute__((address_space(3)))
+typedef LDS f4 lds_f4;
+typedef LDS float lds_float;
+typedef LDS int lds_int;
+
+__device__ __forceinline__ int ring_slot(int x, int y, int z) {
+    return ((z & (kB - 1)) * kB + (y & (kB - 1))) * kB + (x & (kB - 1));
+}
+
+// Window bookkeeping shared by the accumulator kinds: origin, fit and slab iteration.
+struct Window {
+    int o[3];  // window origin (voxel coordinates), wave-uniform
+    __device__ __forceinline__ bool inside(const int lo[3], const int hi[3]) const {
+        return lo[0] >= o[0] && hi[0] < o[0] + kB && lo[1] >= o[1] && hi[1] < o[1] + kB && lo[2] >= o[2] &&
+               hi[2] < o[2] + kB;
+    }
+    // coordinate of the window along axis a that sits in ring slot sa
+    __device__ __forceinline__ int coord(int a, int sa) const { return o[a] + ((sa - o[a]) & (kB - 1)); }
+    // flush(x, y, z) for every window voxel, one per lane per round
+    template <class Flush>
+    __device__ void each_voxel(Flush& flush) const {
+        for (int i = lane_id(); i < kB3; i += 64) {
+            const int sx = i & (kB - 1), sy = (i >> 3) & (kB - 1), sz = i >> 6;
+            flush(coord(0, sx), coord(1, sy), coord(2, sz));
+        }
+    }
+    template <class Flush>
+    __device__ void move_axis(int a, int no, Flush& flush) {
+        const int d = no - o[a];
+        if (d == 0) return;
+        if (d >= kB || d <= -kB) {
+            each_voxel(flush);
+        } else {
+            const int first = d > 0 ? o[a] : o[a] + kB + d;
+            const int cnt = d > 0 ? d : -d;
+            const int p = lane_id() & (kB - 1), q = lane_id() >> 3;
+            const int b1 = a == 0 ? 1 : 0, b2 = a == 2 ? 1 : 2;
+            const int v1 = coord(b1, p), v2 = coord(b2, q);
+            for (int t = 0; t < cnt; ++t) {
+                int c[3];
+                c[a] = first + t;
+                c[b1] = v1;
+                c[b2] = v2;
+                flush(c[0], c[1], c[2]);
+            }
+        }
+        o[a] = no;
+    }
+    // Make the window cover the corner boxes [lo, hi] of every lane that is on.
+    template <class Flush>
+    __device__ __forceinline__ void fit(bool on, const int lo[3], const int hi[3], Flush& flush) {
+        const bool fits = !on || inside(lo, hi);
+        if (!wave_any(!fits)) return;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const int mn = wave_min_i(on ? lo[a] : (1 << 30));
+            const int mx = wave_max_i(on ? hi[a] : -(1 << 30));
+            if (mn > mx) continue;  // no lane on
+            int no = o[a];
+            if (mx - mn < kB) {
+                if (mn < no) no = mn;
+                else if (mx > no + kB - 1) no = mx - kB + 1;
+            } else if (mn < no || mn > no + kB - 1) {
+                no = mn;  // cannot cover every lane: keep the low end, the rest go to HBM
+            }
+            move_axis(a, no, flush);
+        }
+    }
+};
+
+// The J^T accumulator: float4 (three colour channels and sigma) per window voxel.  LDS
+// float atomics are slow when many lanes of an instruction add, so updates are plain
+// read-modify-writes by one elected lane per slot: every pending lane writes its lane id
+// into the slot's tag, the lanes that read their own id back own a distinct slot this
+// round and update it, the others retry.  Each lane visits its eight corners in an order
+// rotated by its pixel position, so lanes of one cell (which share all eight corners)
+// mostly target different voxels in the same round.
+struct Brick4 {
+    Window win;
+    volatile lds_f4* s;    // [kB3]
+    volatile lds_int* tag; // [kB3]
+
+    __device__ __forceinline__ void init(f4* sb, int* tb) {
+        s = (volatile lds_f4*)sb;
+        tag = (volatile lds_int*)tb;
+        win.o[0] = win.o[1] = win.o[2] = -(1 << 24);
+        for (int i = lane_id(); i < kB3; i += 64) s[i] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+    }
+    template <class Sink>
+    __device__ __forceinline__ void flush_voxel(const Geo& G, int x, int y, int z, Sink& out) {
+        const int sl = ring_slot(x, y, z);
+        const f4 v = s[sl];
+        s[sl] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+        if ((v.x != 0.0f || v.y != 0.0f || v.z != 0.0f || v.w != 0.0f) && x >= 0 && y >= 0 && z >= 0 &&
+            x < G.nx && y < G.ny && z < G.nz) {
+            const float vv[4] = {v.x, v.y, v.z, v.w};
+            out((z * G.ny + y) * G.nx + x, vv);
+        }
+    }
+    template <class Sink>
+    __device__ __forceinline__ void fit(const Geo& G, bool on, const int lo[3], const int hi[3], Sink& out) {
+        auto fl = [&](int x, int y, int z) { flush_voxel(G, x, y, z, out); };
+        win.fit(on, lo, hi, fl);
+    }
+    template <class Sink>
+    __device__ void flush_all(const Geo& G, Sink& out) {
+        auto fl = [&](int x, int y, int z) { flush_voxel(G, x, y, z, out); };
+        win.each_voxel(fl);
+    }
+    // add val * weight(corner) to the 8 corners of every lane that is on (uniform call)
+    template <class Sink>
+    __device__ __forceinline__ void scatter8(const Geo& G, bool on, bool inb, const Corners& c, f4 val, Sink& out) {
+        const int lane = lane_id();
+        const int phi = ((lane & 7) + 3 * (lane >> 3)) & 7;
+#pragma unroll 1
+        for (int r = 0; r < 8; ++r) {
+            const int i = (r + phi) & 7;
+            const int x = c.i[0] + (i & 1), y = c.i[1] + ((i >> 1) & 1), z = c.i[2] + (i >> 2);
+            const f4 add = val * corner_weight(c, i);
+            if (on && !inb) {
+                const float vv[4] = {add.x, add.y, add.z, add.w};
+                out((z * G.ny + y) * G.nx + x, vv);
+            }
+            bool pend = on && inb;
+            const int sl = ring_slot(x, y, z);
+            while (wave_any(pend)) {
+                if (pend) tag[sl] = lane;
+                if (pend && tag[sl] == lane) {
+                    s[sl] = s[sl] + add;
+                    pend = false;
+                }
+            }
+        }
+    }
+};
+
+// Generic accumulator with NCH scalar channels updated by LDS atomics (used by the
+// once-per-step gradient and feature passes).
+template <int NCH>
+struct Brick {
+    Window win;
+    lds_float* s;  // [NCH][kB3]
+
+    __device__ __forceinline__ void init(float* base) {
+        s = (lds_float*)base;
+        win.o[0] = win.o[1] = win.o[2] = -(1 << 24);
+        for (int i = lane_id(); i < NCH * kB3; i += 64) s[i] = 0.0f;
+    }
+    __device__ __forceinline__ bool inside(const int lo[3], const int hi[3]) const { return win.inside(lo, hi); }
+    __device__ __forceinline__ void add(int x, int y, int z, const float v[NCH]) {
+        const int sl = ring_slot(x, y, z);
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) lds_add(s + c * kB3 + sl, v[c]);
+    }
+    template <class F>
+    __device__ __forceinline__ void flush_voxel(const Geo& G, int x, int y, int z, F& out) {
+        const int sl = ring_slot(x, y, z);
+        float v[NCH];
+        bool nz = false;
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            v[c] = lds_take(s + c * kB3 + sl);
+            nz |= v[c] != 0.0f;
+        }
+        if (nz && x >= 0 && y >= 0 && z >= 0 && x < G.nx && y < G.ny && z < G.nz) out((z * G.ny + y) * G.nx + x, v);
+    }
+    template <class F>
+    __device__ void flush_all(const Geo& G, F& out) {
+        auto fl = [&](int x, int y, int z) { flush_voxel(G, x, y, z, out); };
+        win.each_voxel(fl);
+    }
+    template <class F>
+    __device__ __forceinline__ void fit(const Geo& G, bool on, const int lo[3], const int hi[3], F& out) {
+        auto fl = [&](int x, int y, int z) { flush_voxel(G, x, y, z, out); };
+        win.fit(on, lo, hi, fl);
+    }
+};
+
+__device__ __forceinline__ int __hip_atomic_compare_exchange_strong_ret(lds_int* p, int expected, int desired) {
+    __hip_atomic_compare_exchange_strong(p, &expected, desired, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_WAVEFRONT);
+    return expected;  // the value found: equals the old expected value on success
+}
+
+// Per-wave LDS hash table for the environment texels a wave's rays hit (64 slots, linear
+// probing; a texel that finds no slot goes straight to a global atomic).
+template <int NCH>
+struct TexTable {
+    lds_int* keys;  // [64]
+    lds_float* s;   // [NCH][64]
+    __device__ __forceinline__ void init(int* kbase, float* sbase) {
+        keys = (lds_int*)kbase;
+        s = (lds_float*)sbase;
+        keys[lane_id()] = -1;
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) s[c * 64 + lane_id()] = 0.0f;
+    }
+    template <class F>
+    __device__ __forceinline__ void insert(int t, const float v[NCH], F& out) {
+        int sl = (int)(((unsigned)t * 2654435761u) >> 26);
+#pragma unroll
+        for (int probe = 0; probe < 4; ++probe) {
+            const int prev = __hip_atomic_compare_exchange_strong_ret(keys + sl, -1, t);
+            if (prev == -1 || prev == t) {
+#pragma unroll
+                for (int c = 0; c < NCH; ++c) lds_add(s + c * 64 + sl, v[c]);
+                return;
+            }
+            sl = (sl + 1) & 63;
+        }
+        out(t, v);
+    }
+    template <class F>
+    __device__ __forceinline__ void flush(F& out) {
+        const int l = lane_id();
+        const int t = __hip_atomic_exchange(keys + l, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+        float v[NCH];
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) v[c] = lds_take(s + c * 64 + l);
+        if (t >= 0) out(t, v);
+    }
+};
+
+// Global sinks: add a unit's channels to HBM.
+struct SinkY {  // y[4u + c], c < 4
+    float* y;
+    __device__ __forceinline__ void operator()(int u, const float* v) const {
+        float* p = y + 4 * (size_t)u;
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+            if (v[c] != 0.0f) atomic_add(p + c, v[c]);
+    }
+};
+struct SinkGrad {  // grad[4u + c] (c < 4) and blocks[5u + c] (channels 4..8)
+    float* grad;
+    float* blocks;
+    __device__ __forceinline__ void operator()(int u, const float* v) const {
+        if (grad) {
+            float* g = grad + 4 * (size_t)u;
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                if (v[c] != 0.0f) atomic_add(g + c, v[c]);
+        }
+        if (blocks) {
+            float* b = blocks + 5 * (size_t)u;
+#pragma unroll
+            for (int c = 0; c < 5; ++c)
+                if (v[4 + c] != 0.0f) atomic_add(b + c, v[4 + c]);
+        }
+    }
+};
+struct SinkFeat {  // sums[6u + c]
+    float* sums;
+    __device__ __forceinline__ void operator()(int u, const float* v) const {
+        float* p = sums + 6 * (size_t)u;
+#pragma unroll
+        for (int c = 0; c < 6; ++c)
+            if (v[c] != 0.0f) atomic_add(p + c, v[c]);
+    }
+};
+
 // ------------------------------------------------------------------ forward pass (+ tangent)
 // Optical depth in front of a sample, summed with compensation (Kahan) so that the
 // adjoint pass can step it back sample by sample with an error of order eps * V_total.
@@ -199,36 +512,56 @@ struct Depth {
     __device__ __forceinline__ float value() const { return s - c; }
 };
 
+// Gather the trilinear sample of (c, sigma) at corners c.
+template <int PD>
+__device__ __forceinline__ void gather(XL<PD> X, const Corners& c, int nx, int nxy, float& sg, float& c0, float& c1,
+                                       float& c2) {
+    sg = c0 = c1 = c2 = 0.0f;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const float4 q = X(c.v + corner_off(j, nx, nxy));
+        c0 += c.w[j] * q.x;
+        c1 += c.w[j] * q.y;
+        c2 += c.w[j] * q.z;
+        sg += c.w[j] * q.w;
+    }
+}
+
+// The march of a wave is aligned in depth: lane i starts its first sample at wave step
+// off_i = (t_n,i - min t_n) / (h step), so at every step the lanes sample their rays at
+// about the same distance from the camera (the rays of an 8x8 tile are nearly parallel).
+// Every lane still takes its own samples in its own order; only their timing changes.
 template <int PD, bool TAN>
-__device__ __forceinline__ void forward(const Geo& G, const Ray& r, XL<PD> X, const float4* __restrict__ V, float H[3],
-                                        float& Texit, float Hd[3], Depth& depth) {
+__device__ __forceinline__ void forward(const Geo& G, const Ray& r, bool live, XL<PD> X, const float4* __restrict__ V,
+                                        float H[3], float& Texit, float Hd[3], Depth& depth) {
     float T = 1.0f, Td = 0.0f;
     depth.s = 0.0f;
     depth.c = 0.0f;
     H[0] = H[1] = H[2] = 0.0f;
     Hd[0] = Hd[1] = Hd[2] = 0.0f;
     const int nx = G.nx, nxy = G.nx * G.ny;
-    for (int k = 0; k < r.K; ++k) {
+    const float unit = G.h * G.step;
+    const float t_min = wave_min_f(r.K > 0 ? r.tn : INFINITY);
+    const int off = r.K > 0 ? (int)((r.tn - t_min) / unit + 0.5f) : 0;
+    const int J = wave_max_i(r.K > 0 ? off + r.K : 0);
+    for (int j = 0; j < J; ++j) {
+        const int k = j - off;
+        if (k < 0 || k >= r.K) continue;
         float g[3];
         const float dk = sample_at(G, r, k, g);
         Corners c;
         corners(G, g, c);
-        float sg = 0.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
+        float sg, c0, c1, c2;
+        gather<PD>(X, c, nx, nxy, sg, c0, c1, c2);
         float sgd = 0.0f, cd0 = 0.0f, cd1 = 0.0f, cd2 = 0.0f;
+        if constexpr (TAN) {
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const int vi = c.v + corner_off(j, nx, nxy);
-            const float4 q = X(vi);
-            c0 += c.w[j] * q.x;
-            c1 += c.w[j] * q.y;
-            c2 += c.w[j] * q.z;
-            sg += c.w[j] * q.w;
-            if constexpr (TAN) {
-                const float4 t = V[vi];
-                cd0 += c.w[j] * t.x;
-                cd1 += c.w[j] * t.y;
-                cd2 += c.w[j] * t.z;
-                sgd += c.w[j] * t.w;
+            for (int i = 0; i < 8; ++i) {
+                const float4 t = V[c.v + corner_off(i, nx, nxy)];
+                cd0 += c.w[i] * t.x;
+                cd1 += c.w[i] * t.y;
+                cd2 += c.w[i] * t.z;
+                sgd += c.w[i] * t.w;
             }
         }
         const float tau = sg * dk;
@@ -250,6 +583,7 @@ __device__ __forceinline__ void forward(const Geo& G, const Ray& r, XL<PD> X, co
         T *= e;
     }
     Texit = T;
+    if (!live) return;
     const float tmin = r.hit ? r.tf : 0.0f;
     for (int l = 0; l < G.n_layers; ++l) {
         Tex tx;
@@ -294,15 +628,13 @@ __device__ __forceinline__ void forward(const Geo& G, const Ray& r, XL<PD> X, co
     }
 }
 
-// ------------------------------------------------------------------ adjoint pass: y += J_ray^T u
-// Environment layers first (S, the radiance behind a layer, by the over-recurrence from
-// the background), then the voxel samples from the last to the first as in Alg. 1: the
-// colour behind sample k, G_k, is accumulated from the back (a sum of T-scaled terms, so
-// it keeps its relative precision deep behind opaque matter), and T_k = exp(-V_k) with
-// V_k the compensated optical depth stepped back from the total.
-template <int PD>
-__device__ __forceinline__ float env_adjoint(const Geo& G, const Ray& r, XL<PD> X, const float u[3], float Tx,
-                                             float* __restrict__ y) {
+// ------------------------------------------------------------------ environment part of the adjoint
+// T_l in front of every layer the ray hits (front to back from the grid exit), then the
+// layers back to front with S, the radiance behind a layer (over-recurrence from the
+// background).  emit(l, tx, c, alpha, T_l, S) hands each layer's data to the mode; returns
+// S seen from the grid exit (unattenuated).
+template <int PD, class Emit>
+__device__ __forceinline__ void env_back(const Geo& G, const Ray& r, XL<PD> X, float Tx, float S[3], Emit& emit) {
     float Tl[kMaxLayers];
     unsigned used = 0;
     float T = Tx;
@@ -322,122 +654,136 @@ __device__ __forceinline__ float env_adjoint(const Geo& G, const Ray& r, XL<PD> 
             }
         }
     }
-    float uS = u[0] * G.bg[0] + u[1] * G.bg[1] + u[2] * G.bg[2];
+    S[0] = G.bg[0];
+    S[1] = G.bg[1];
+    S[2] = G.bg[2];
 #pragma unroll
     for (int l = kMaxLayers - 1; l >= 0; --l) {
         if (used & (1u << l)) {
             Tex tx;
             env_hit(G, r, l, tmin, tx);
-            float al = 0.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
+            float al = 0.0f, c[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const float4 q = X(tx.t[j]);
-                c0 += tx.w[j] * q.x;
-                c1 += tx.w[j] * q.y;
-                c2 += tx.w[j] * q.z;
+                c[0] += tx.w[j] * q.x;
+                c[1] += tx.w[j] * q.y;
+                c[2] += tx.w[j] * q.z;
                 al += tx.w[j] * q.w;
             }
-            const float uc = u[0] * c0 + u[1] * c1 + u[2] * c2;
-            const float A = Tl[l] * al;              // dH/dc_l
-            const float dA = Tl[l] * (uc - uS);      // u . dH/dalpha_l
+            emit(tx, c, al, Tl[l], S);
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                float* yy = y + 4 * (size_t)tx.t[j];
-                const float wA = tx.w[j] * A;
-                atomic_add(yy + 0, wA * u[0]);
-                atomic_add(yy + 1, wA * u[1]);
-                atomic_add(yy + 2, wA * u[2]);
-                atomic_add(yy + 3, tx.w[j] * dA);
-            }
-            uS = al * uc + (1.0f - al) * uS;
+            for (int ch = 0; ch < 3; ++ch) S[ch] = al * c[ch] + (1.0f - al) * S[ch];
         }
     }
-    return uS;  // u . (environment radiance seen from the grid exit)
 }
 
+// ------------------------------------------------------------------ J^T u (and J^T J v) scatter
+// Voxel samples from the last to the first, as in Alg. 1: G_k (colour composited behind
+// sample k) is accumulated from the back starting at the environment seen from the exit,
+// and T_k = exp(-V_k) with V_k the compensated optical depth stepped back.
 template <int PD>
-__device__ __forceinline__ void adjoint_scatter(const Geo& G, const Ray& r, XL<PD> X, const float u[3], Depth depth,
-                                                float* __restrict__ y) {
+__device__ __forceinline__ void adjoint_scatter(const Geo& G, const Ray& r, bool live, XL<PD> X, const float u[3],
+                                                Depth depth, Brick4& B, TexTable<4>& TT, float* __restrict__ y) {
+    SinkY sink{y};
     const float Tx = expf(-depth.value());
-    const float uE = env_adjoint<PD>(G, r, X, u, Tx, y);
-    float uG = Tx * uE;   // u . G_k, the colour composited behind sample k
-    float Tn = Tx;        // T_{k+1}
-    const int nx = G.nx, nxy = G.nx * G.ny;
-    for (int k = r.K - 1; k >= 0; --k) {
-        float g[3];
-        const float dk = sample_at(G, r, k, g);
-        Corners c;
-        corners(G, g, c);
-        float sg = 0.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
+    float uE = 0.0f;
+    if (live) {
+        float S[3];
+        auto emit = [&](const Tex& tx, const float c[3], float al, float Tl, const float Sb[3]) {
+            const float uc = u[0] * c[0] + u[1] * c[1] + u[2] * c[2];
+            const float uS = u[0] * Sb[0] + u[1] * Sb[1] + u[2] * Sb[2];
+            const float A = Tl * al;          // dH/dc_l
+            const float dA = Tl * (uc - uS);  // u . dH/dalpha_l
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const float4 q = X(c.v + corner_off(j, nx, nxy));
-            c0 += c.w[j] * q.x;
-            c1 += c.w[j] * q.y;
-            c2 += c.w[j] * q.z;
-            sg += c.w[j] * q.w;
-        }
-        const float tau = sg * dk;
-        depth.add(-tau);
-        const float T = (k == 0) ? 1.0f : expf(-depth.value());
-        const float al = -expm1f(-tau);
-        const float A = T * al;
-        const float uc = u[0] * c0 + u[1] * c1 + u[2] * c2;
-        const float ds = dk * (Tn * uc - uG);
-        uG += A * uc;
-        Tn = T;
-        const float Au0 = A * u[0], Au1 = A * u[1], Au2 = A * u[2];
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            float* yy = y + 4 * (size_t)(c.v + corner_off(j, nx, nxy));
-            const float w = c.w[j];
-            atomic_add(yy + 0, w * Au0);
-            atomic_add(yy + 1, w * Au1);
-            atomic_add(yy + 2, w * Au2);
-            atomic_add(yy + 3, w * ds);
-        }
+            for (int j = 0; j < 4; ++j) {
+                const float wA = tx.w[j] * A;
+                const float v[4] = {wA * u[0], wA * u[1], wA * u[2], tx.w[j] * dA};
+                TT.insert(tx.t[j], v, sink);
+            }
+        };
+        env_back<PD>(G, r, X, Tx, S, emit);
+        uE = u[0] * S[0] + u[1] * S[1] + u[2] * S[2];
     }
+    TT.flush(sink);
+    float uG = Tx * uE;  // u . G_k
+    float Tn = Tx;       // T_{k+1}
+    const int nx = G.nx, nxy = G.nx * G.ny;
+    const float unit = G.h * G.step;
+    const float t_max = wave_max_f(r.K > 0 ? r.tf : -INFINITY);
+    const int off = r.K > 0 ? (int)((t_max - r.tf) / unit + 0.5f) : 0;
+    const int J = wave_max_i(r.K > 0 ? off + r.K : 0);
+    for (int j = 0; j < J; ++j) {
+        const int m = j - off;
+        const bool on = m >= 0 && m < r.K;
+        const int k = r.K - 1 - m;
+        Corners c{};
+        float dk = 0.0f;
+        int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+        if (on) {
+            float g[3];
+            dk = sample_at(G, r, k, g);
+            corners(G, g, c);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                lo[a] = c.i[a];
+                hi[a] = c.i[a] + 1;
+            }
+        }
+        B.fit(G, on, lo, hi, sink);
+        f4 val = {0.0f, 0.0f, 0.0f, 0.0f};
+        if (on) {
+            float sg, c0, c1, c2;
+            gather<PD>(X, c, nx, nxy, sg, c0, c1, c2);
+            const float tau = sg * dk;
+            depth.add(-tau);
+            const float T = (k == 0) ? 1.0f : expf(-depth.value());
+            const float al = -expm1f(-tau);
+            const float A = T * al;
+            const float uc = u[0] * c0 + u[1] * c1 + u[2] * c2;
+            const float ds = dk * (Tn * uc - uG);
+            uG += A * uc;
+            Tn = T;
+            val = f4{A * u[0], A * u[1], A * u[2], ds};
+        }
+        B.scatter8(G, on, on && B.win.inside(lo, hi), c, val, sink);
+    }
+    B.flush_all(G, sink);
 }
 
 // ------------------------------------------------------------------ gradient + exact blocks
 // Per-ray window over the current 8 corners.  A voxel is a corner of a contiguous run of
 // a ray's samples (its corner region is a box and the ray is a line), so a voxel that
 // leaves the window never returns: flushing on leave aggregates the ray's partials per
-// voxel exactly before they are squared into the block.
+// voxel exactly before they are squared into the block.  The flushed per-ray products
+// (gradient and block entries, linear in the rays) are then combined per wave in LDS.
 struct Win {
     int i[3];
     float a[8], s0[8], s1[8], s2[8];
 };
 
-__device__ __forceinline__ void flush_unit(int unit, float a, float s0, float s1, float s2, const float rr[3],
-                                           float* __restrict__ grad, float* __restrict__ blocks) {
-    if (a == 0.0f && s0 == 0.0f && s1 == 0.0f && s2 == 0.0f) return;
-    if (grad) {
-        float* g = grad + 4 * (size_t)unit;
-        atomic_add(g + 0, -a * rr[0]);
-        atomic_add(g + 1, -a * rr[1]);
-        atomic_add(g + 2, -a * rr[2]);
-        atomic_add(g + 3, -(s0 * rr[0] + s1 * rr[1] + s2 * rr[2]));
+struct GradOut {
+    const Geo& G;
+    Brick<9>& B;
+    SinkGrad sink;
+    float rr[3];
+    __device__ __forceinline__ void unit(int x, int y, int z, float a, float s0, float s1, float s2) {
+        if (a == 0.0f && s0 == 0.0f && s1 == 0.0f && s2 == 0.0f) return;
+        const float v[9] = {-a * rr[0],    -a * rr[1], -a * rr[2], -(s0 * rr[0] + s1 * rr[1] + s2 * rr[2]),
+                            a * a,         a * s0,     a * s1,     a * s2,
+                            s0 * s0 + s1 * s1 + s2 * s2};
+        const int lo[3] = {x, y, z};
+        if (B.inside(lo, lo)) B.add(x, y, z, v);
+        else sink((z * G.ny + y) * G.nx + x, v);
     }
-    if (blocks) {
-        float* b = blocks + 5 * (size_t)unit;
-        atomic_add(b + 0, a * a);
-        atomic_add(b + 1, a * s0);
-        atomic_add(b + 2, a * s1);
-        atomic_add(b + 3, a * s2);
-        atomic_add(b + 4, s0 * s0 + s1 * s1 + s2 * s2);
-    }
-}
+};
 
-__device__ __forceinline__ void win_flush_slot(const Geo& G, Win& w, int b, const float rr[3], float* grad,
-                                               float* blocks) {
-    const int unit = ((w.i[2] + ((b >> 2) & 1)) * G.ny + (w.i[1] + ((b >> 1) & 1))) * G.nx + (w.i[0] + (b & 1));
-    flush_unit(unit, w.a[b], w.s0[b], w.s1[b], w.s2[b], rr, grad, blocks);
+__device__ __forceinline__ void win_flush_slot(Win& w, int b, GradOut& out) {
+    out.unit(w.i[0] + (b & 1), w.i[1] + ((b >> 1) & 1), w.i[2] + ((b >> 2) & 1), w.a[b], w.s0[b], w.s1[b], w.s2[b]);
 }
 
 template <int AX>
-__device__ __forceinline__ void win_shift(const Geo& G, Win& w, int target, const float rr[3], float* grad,
-                                          float* blocks) {
+__device__ __forceinline__ void win_shift(Win& w, int target, GradOut& out) {
     constexpr int bit = 1 << AX;
     const int delta = target - w.i[AX];
     if (delta == 0) return;
@@ -445,7 +791,7 @@ __device__ __forceinline__ void win_shift(const Geo& G, Win& w, int target, cons
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
             if (!(b & bit)) {
-                win_flush_slot(G, w, b, rr, grad, blocks);
+                win_flush_slot(w, b, out);
                 w.a[b] = w.a[b | bit]; w.s0[b] = w.s0[b | bit]; w.s1[b] = w.s1[b | bit]; w.s2[b] = w.s2[b | bit];
                 w.a[b | bit] = 0.0f; w.s0[b | bit] = 0.0f; w.s1[b | bit] = 0.0f; w.s2[b | bit] = 0.0f;
             }
@@ -454,7 +800,7 @@ __device__ __forceinline__ void win_shift(const Geo& G, Win& w, int target, cons
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
             if (b & bit) {
-                win_flush_slot(G, w, b, rr, grad, blocks);
+                win_flush_slot(w, b, out);
                 w.a[b] = w.a[b ^ bit]; w.s0[b] = w.s0[b ^ bit]; w.s1[b] = w.s1[b ^ bit]; w.s2[b] = w.s2[b ^ bit];
                 w.a[b ^ bit] = 0.0f; w.s0[b ^ bit] = 0.0f; w.s1[b ^ bit] = 0.0f; w.s2[b ^ bit] = 0.0f;
             }
@@ -462,7 +808,7 @@ __device__ __forceinline__ void win_shift(const Geo& G, Win& w, int target, cons
     } else {
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
-            win_flush_slot(G, w, b, rr, grad, blocks);
+            win_flush_slot(w, b, out);
             w.a[b] = 0.0f; w.s0[b] = 0.0f; w.s1[b] = 0.0f; w.s2[b] = 0.0f;
         }
     }
@@ -470,89 +816,78 @@ __device__ __forceinline__ void win_shift(const Geo& G, Win& w, int target, cons
 }
 
 template <int PD>
-__device__ __forceinline__ void grad_scatter(const Geo& G, const Ray& r, XL<PD> X, const float rr[3], Depth depth,
-                                             float* __restrict__ grad, float* __restrict__ blocks) {
+__device__ __forceinline__ void grad_scatter(const Geo& G, const Ray& r, bool live, XL<PD> X, const float rr[3],
+                                             Depth depth, Brick<9>& B, TexTable<9>& TT, float* __restrict__ grad,
+                                             float* __restrict__ blocks) {
+    SinkGrad sink{grad, blocks};
+    GradOut out{G, B, sink, {rr[0], rr[1], rr[2]}};
     const float Tx = expf(-depth.value());
-    float S0 = G.bg[0], S1 = G.bg[1], S2 = G.bg[2];
-    // environment layers (the four texels of one lookup are distinct units)
-    {
-        float Tl[kMaxLayers];
-        unsigned used = 0;
-        float T = Tx;
-        const float tmin = r.hit ? r.tf : 0.0f;
+    float S[3] = {0.0f, 0.0f, 0.0f};
+    if (live) {
+        // environment layers (the four texels of one lookup are distinct units)
+        auto emit = [&](const Tex& tx, const float c[3], float al, float Tl, const float Sb[3]) {
+            const float A = Tl * al;
+            const float d0 = Tl * (c[0] - Sb[0]), d1 = Tl * (c[1] - Sb[1]), d2 = Tl * (c[2] - Sb[2]);
 #pragma unroll
-        for (int l = 0; l < kMaxLayers; ++l) {
-            Tl[l] = 0.0f;
-            if (l < G.n_layers) {
-                Tex tx;
-                if (env_hit(G, r, l, tmin, tx)) {
-                    float al = 0.0f;
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) al += tx.w[j] * X(tx.t[j]).w;
-                    Tl[l] = T;
-                    used |= 1u << l;
-                    T *= (1.0f - al);
-                }
+            for (int j = 0; j < 4; ++j) {
+                const float w = tx.w[j];
+                const float a = w * A, s0 = w * d0, s1 = w * d1, s2 = w * d2;
+                if (a == 0.0f && s0 == 0.0f && s1 == 0.0f && s2 == 0.0f) continue;
+                const float v[9] = {-a * rr[0], -a * rr[1], -a * rr[2], -(s0 * rr[0] + s1 * rr[1] + s2 * rr[2]),
+                                    a * a,      a * s0,     a * s1,     a * s2,
+                                    s0 * s0 + s1 * s1 + s2 * s2};
+                TT.insert(tx.t[j], v, sink);
             }
-        }
-#pragma unroll
-        for (int l = kMaxLayers - 1; l >= 0; --l) {
-            if (used & (1u << l)) {
-                Tex tx;
-                env_hit(G, r, l, tmin, tx);
-                float al = 0.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const float4 q = X(tx.t[j]);
-                    c0 += tx.w[j] * q.x;
-                    c1 += tx.w[j] * q.y;
-                    c2 += tx.w[j] * q.z;
-                    al += tx.w[j] * q.w;
-                }
-                const float A = Tl[l] * al;
-                const float d0 = Tl[l] * (c0 - S0), d1 = Tl[l] * (c1 - S1), d2 = Tl[l] * (c2 - S2);
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const float w = tx.w[j];
-                    flush_unit(tx.t[j], w * A, w * d0, w * d1, w * d2, rr, grad, blocks);
-                }
-                S0 = al * c0 + (1.0f - al) * S0;
-                S1 = al * c1 + (1.0f - al) * S1;
-                S2 = al * c2 + (1.0f - al) * S2;
-            }
-        }
+        };
+        env_back<PD>(G, r, X, Tx, S, emit);
     }
-    if (r.K <= 0) return;
+    TT.flush(sink);
     Win w;
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
         w.a[b] = 0.0f; w.s0[b] = 0.0f; w.s1[b] = 0.0f; w.s2[b] = 0.0f;
     }
+    w.i[0] = w.i[1] = w.i[2] = 0;
+    bool started = false;
     // G_k from the back, starting with the environment seen from the grid exit
-    float G0 = Tx * S0, G1 = Tx * S1, G2 = Tx * S2;
+    float G0 = Tx * S[0], G1 = Tx * S[1], G2 = Tx * S[2];
     float Tn = Tx;
     const int nx = G.nx, nxy = G.nx * G.ny;
-    for (int k = r.K - 1; k >= 0; --k) {
-        float g[3];
-        const float dk = sample_at(G, r, k, g);
+    const float unit = G.h * G.step;
+    const float t_max = wave_max_f(r.K > 0 ? r.tf : -INFINITY);
+    const int off = r.K > 0 ? (int)((t_max - r.tf) / unit + 0.5f) : 0;
+    const int J = wave_max_i(r.K > 0 ? off + r.K : 0);
+    for (int j = 0; j < J; ++j) {
+        const int m = j - off;
+        const bool on = m >= 0 && m < r.K;
+        const int k = r.K - 1 - m;
         Corners c;
-        corners(G, g, c);
-        if (k == r.K - 1) {
-            w.i[0] = c.i[0]; w.i[1] = c.i[1]; w.i[2] = c.i[2];
-        } else {
-            win_shift<0>(G, w, c.i[0], rr, grad, blocks);
-            win_shift<1>(G, w, c.i[1], rr, grad, blocks);
-            win_shift<2>(G, w, c.i[2], rr, grad, blocks);
-        }
-        float sg = 0.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
+        float dk = 0.0f;
+        int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+        if (on) {
+            float g[3];
+            dk = sample_at(G, r, k, g);
+            corners(G, g, c);
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const float4 q = X(c.v + corner_off(j, nx, nxy));
-            c0 += c.w[j] * q.x;
-            c1 += c.w[j] * q.y;
-            c2 += c.w[j] * q.z;
-            sg += c.w[j] * q.w;
+            for (int a = 0; a < 3; ++a) {
+                // cover the corners about to leave the lane's window as well as the new ones
+                const int prev = started ? w.i[a] : c.i[a];
+                lo[a] = min(prev, c.i[a]);
+                hi[a] = max(prev, c.i[a]) + 1;
+            }
         }
+        B.fit(G, on, lo, hi, sink);
+        if (!on) continue;
+        if (!started) {
+            w.i[0] = c.i[0]; w.i[1] = c.i[1]; w.i[2] = c.i[2];
+            started = true;
+        } else {
+            win_shift<0>(w, c.i[0], out);
+            win_shift<1>(w, c.i[1], out);
+            win_shift<2>(w, c.i[2], out);
+        }
+        float sg, c0, c1, c2;
+        gather<PD>(X, c, nx, nxy, sg, c0, c1, c2);
         const float tau = sg * dk;
         depth.add(-tau);
         const float T = (k == 0) ? 1.0f : expf(-depth.value());
@@ -566,113 +901,88 @@ __device__ __forceinline__ void grad_scatter(const Geo& G, const Ray& r, XL<PD> 
         G2 += A * c2;
         Tn = T;
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            w.a[j] += c.w[j] * A;
-            w.s0[j] += c.w[j] * ds0;
-            w.s1[j] += c.w[j] * ds1;
-            w.s2[j] += c.w[j] * ds2;
+        for (int i = 0; i < 8; ++i) {
+            w.a[i] += c.w[i] * A;
+            w.s0[i] += c.w[i] * ds0;
+            w.s1[i] += c.w[i] * ds1;
+            w.s2[i] += c.w[i] * ds2;
+        }
+        if (k == 0) {
+#pragma unroll
+            for (int b = 0; b < 8; ++b) win_flush_slot(w, b, out);
         }
     }
-#pragma unroll
-    for (int b = 0; b < 8; ++b) win_flush_slot(G, w, b, rr, grad, blocks);
+    B.flush_all(G, sink);
 }
 
 // ------------------------------------------------------------------ features for the learned preconditioner
-// Per sample and corner (weight w): sums[unit] += (w, w T, w G (3), w alpha), G = colour behind.
+// Per sample and corner (weight w): (w, w T, w G (3), w alpha), G the colour composited
+// behind the sample (attenuated); for a texel, T_l and T_l S (S behind the layer).
 template <int PD>
-__device__ __forceinline__ void feature_scatter(const Geo& G, const Ray& r, XL<PD> X, const float H[3], float Texit,
-                                                float* __restrict__ sums) {
-    {
-        float T = Texit;
-        float Tl[kMaxLayers], Al[kMaxLayers];
-        unsigned used = 0;
-        const float tmin = r.hit ? r.tf : 0.0f;
+__device__ __forceinline__ void feature_scatter(const Geo& G, const Ray& r, bool live, XL<PD> X, Depth depth,
+                                                Brick<6>& B, TexTable<6>& TT, float* __restrict__ sums) {
+    SinkFeat sink{sums};
+    const float Tx = expf(-depth.value());
+    float S[3] = {0.0f, 0.0f, 0.0f};
+    if (live) {
+        auto emit = [&](const Tex& tx, const float c[3], float al, float Tl, const float Sb[3]) {
 #pragma unroll
-        for (int l = 0; l < kMaxLayers; ++l) {
-            Tl[l] = 0.0f;
-            Al[l] = 0.0f;
-            if (l < G.n_layers) {
-                Tex tx;
-                if (env_hit(G, r, l, tmin, tx)) {
-                    float al = 0.0f;
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) al += tx.w[j] * X(tx.t[j]).w;
-                    Tl[l] = T;
-                    Al[l] = al;
-                    used |= 1u << l;
-                    T *= (1.0f - al);
-                }
+            for (int j = 0; j < 4; ++j) {
+                const float w = tx.w[j];
+                if (w == 0.0f) continue;
+                const float v[6] = {w, w * Tl, w * Tl * Sb[0], w * Tl * Sb[1], w * Tl * Sb[2], w * al};
+                TT.insert(tx.t[j], v, sink);
             }
-        }
-        float S0 = G.bg[0], S1 = G.bg[1], S2 = G.bg[2];
-#pragma unroll
-        for (int l = kMaxLayers - 1; l >= 0; --l) {
-            if (used & (1u << l)) {
-                Tex tx;
-                env_hit(G, r, l, tmin, tx);
-                float c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const float4 q = X(tx.t[j]);
-                    c0 += tx.w[j] * q.x;
-                    c1 += tx.w[j] * q.y;
-                    c2 += tx.w[j] * q.z;
-                }
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    float* s = sums + 6 * (size_t)tx.t[j];
-                    const float w = tx.w[j];
-                    atomic_add(s + 0, w);
-                    atomic_add(s + 1, w * Tl[l]);
-                    atomic_add(s + 2, w * S0);
-                    atomic_add(s + 3, w * S1);
-                    atomic_add(s + 4, w * S2);
-                    atomic_add(s + 5, w * Al[l]);
-                }
-                const float al = Al[l];
-                S0 = al * c0 + (1.0f - al) * S0;
-                S1 = al * c1 + (1.0f - al) * S1;
-                S2 = al * c2 + (1.0f - al) * S2;
-            }
-        }
+        };
+        env_back<PD>(G, r, X, Tx, S, emit);
     }
-    float T = 1.0f, P0 = 0.0f, P1 = 0.0f, P2 = 0.0f;
+    TT.flush(sink);
+    float G0 = Tx * S[0], G1 = Tx * S[1], G2 = Tx * S[2];
     const int nx = G.nx, nxy = G.nx * G.ny;
-    for (int k = 0; k < r.K; ++k) {
-        float g[3];
-        const float dk = sample_at(G, r, k, g);
+    const float unit = G.h * G.step;
+    const float t_max = wave_max_f(r.K > 0 ? r.tf : -INFINITY);
+    const int off = r.K > 0 ? (int)((t_max - r.tf) / unit + 0.5f) : 0;
+    const int J = wave_max_i(r.K > 0 ? off + r.K : 0);
+    for (int j = 0; j < J; ++j) {
+        const int m = j - off;
+        const bool on = m >= 0 && m < r.K;
+        const int k = r.K - 1 - m;
         Corners c;
-        corners(G, g, c);
-        float sg = 0.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
+        float dk = 0.0f;
+        int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+        if (on) {
+            float g[3];
+            dk = sample_at(G, r, k, g);
+            corners(G, g, c);
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const float4 q = X(c.v + corner_off(j, nx, nxy));
-            c0 += c.w[j] * q.x;
-            c1 += c.w[j] * q.y;
-            c2 += c.w[j] * q.z;
-            sg += c.w[j] * q.w;
+            for (int a = 0; a < 3; ++a) {
+                lo[a] = c.i[a];
+                hi[a] = c.i[a] + 1;
+            }
         }
+        B.fit(G, on, lo, hi, sink);
+        if (!on) continue;
+        float sg, c0, c1, c2;
+        gather<PD>(X, c, nx, nxy, sg, c0, c1, c2);
         const float tau = sg * dk;
-        const float e = expf(-tau);
+        depth.add(-tau);
+        const float T = (k == 0) ? 1.0f : expf(-depth.value());
         const float al = -expm1f(-tau);
         const float A = T * al;
-        const float G0 = H[0] - P0 - A * c0, G1 = H[1] - P1 - A * c1, G2 = H[2] - P2 - A * c2;
+        const bool inb = B.inside(lo, hi);
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            float* s = sums + 6 * (size_t)(c.v + corner_off(j, nx, nxy));
-            const float w = c.w[j];
-            atomic_add(s + 0, w);
-            atomic_add(s + 1, w * T);
-            atomic_add(s + 2, w * G0);
-            atomic_add(s + 3, w * G1);
-            atomic_add(s + 4, w * G2);
-            atomic_add(s + 5, w * al);
+        for (int i = 0; i < 8; ++i) {
+            const float w = c.w[i];
+            const float v[6] = {w, w * T, w * G0, w * G1, w * G2, w * al};
+            const int x = c.i[0] + (i & 1), yy = c.i[1] + ((i >> 1) & 1), z = c.i[2] + (i >> 2);
+            if (inb) B.add(x, yy, z, v);
+            else sink((z * G.ny + yy) * G.nx + x, v);
         }
-        P0 += A * c0;
-        P1 += A * c1;
-        P2 += A * c2;
-        T *= e;
+        G0 += A * c0;
+        G1 += A * c1;
+        G2 += A * c2;
     }
+    B.flush_all(G, sink);
 }
 
 // ------------------------------------------------------------------ workgroup FP64 sum
@@ -683,7 +993,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 __device__ __forceinline__ void block_sum_store(double v, double* out) {
-    __shared__ double red[kBlock / 64];
+    __shared__ double red[kWaves];
     v = wave_sum(v);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     if (lane == 0) red[wave] = v;
@@ -691,7 +1001,7 @@ __device__ __forceinline__ void block_sum_store(double v, double* out) {
     if (threadIdx.x == 0) {
         double s = 0.0;
 #pragma unroll
-        for (int i = 0; i < kBlock / 64; ++i) s += red[i];
+        for (int i = 0; i < kWaves; ++i) s += red[i];
         *out = s;
     }
 }
@@ -702,6 +1012,7 @@ struct Pix {
     long long ray;
 };
 
+// Workgroup b covers a 16x8 pixel tile of camera b / n_tiles; wave w its 8x8 half w.
 __device__ __forceinline__ Pix pixel_of(const Geo& G) {
     Pix p;
     const int b = blockIdx.x;
@@ -709,31 +1020,50 @@ __device__ __forceinline__ Pix pixel_of(const Geo& G) {
     const int tile = b - p.cam * G.n_tiles;
     const int ty = tile / G.tiles_x, tx = tile - ty * G.tiles_x;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    p.px = tx * kTile + (wave & 1) * 8 + (lane & 7);
-    p.py = ty * kTile + (wave >> 1) * 8 + (lane >> 3);
+    p.px = tx * kTileX + wave * 8 + (lane & 7);
+    p.py = ty * kTileY + (lane >> 3);
     p.active = p.px < G.width && p.py < G.height;
     p.ray = ((long long)p.cam * G.height + p.py) * G.width + p.px;
     return p;
 }
 
+template <int MODE>
+struct Lds {
+    static constexpr int NCH = MODE == M_GRAD ? 9 : (MODE == M_FEAT ? 6 : 4);
+    static constexpr bool SCATTER = MODE == M_VJP || MODE == M_JTJ || MODE == M_GRAD || MODE == M_FEAT;
+};
+
 template <int MODE, int PD>
 __global__ __launch_bounds__(kBlock) void k_ray(Geo G, RayArgs A) {
+    constexpr int NCH = Lds<MODE>::NCH;
+    constexpr bool SCATTER = Lds<MODE>::SCATTER;
+    constexpr bool JT = MODE == M_VJP || MODE == M_JTJ;
+    __shared__ float s_brick[(SCATTER && !JT) ? kWaves * NCH * kB3 : 1];
+    __shared__ f4 s_brick4[JT ? kWaves * kB3 : 1];
+    __shared__ int s_tag[JT ? kWaves * kB3 : 1];
+    __shared__ float s_tab[SCATTER ? kWaves * NCH * 64 : 1];
+    __shared__ int s_keys[SCATTER ? kWaves * 64 : 1];
     if (A.done && *A.done) return;
     const Pix p = pixel_of(G);
+    const int wave = threadIdx.x >> 6;
     XL<PD> X;
     X.p = reinterpret_cast<decltype(X.p)>(A.x);
+    Ray r;
+    make_ray(G, A.cams[p.cam], p.px, p.py, r);
+    if (!p.active) {
+        r.K = 0;
+        r.hit = false;
+    }
+    float H[3], Hd[3], Texit;
+    Depth depth;
+    if constexpr (MODE == M_JVP || MODE == M_JTJ) {
+        forward<PD, true>(G, r, p.active, X, reinterpret_cast<const float4*>(A.v), H, Texit, Hd, depth);
+    } else {
+        forward<PD, false>(G, r, p.active, X, nullptr, H, Texit, Hd, depth);
+    }
     double rr_sum = 0.0;
-    if (p.active) {
-        Ray r;
-        make_ray(G, A.cams[p.cam], p.px, p.py, r);
-        float H[3], Hd[3], Texit;
-        Depth depth;
-        if constexpr (MODE == M_JVP || MODE == M_JTJ) {
-            forward<PD, true>(G, r, X, reinterpret_cast<const float4*>(A.v), H, Texit, Hd, depth);
-        } else {
-            forward<PD, false>(G, r, X, nullptr, H, Texit, Hd, depth);
-        }
-        if constexpr (MODE == M_RENDER) {
+    if constexpr (MODE == M_RENDER) {
+        if (p.active) {
             if (A.targets) {
                 float res[3];
 #pragma unroll
@@ -749,24 +1079,47 @@ __global__ __launch_bounds__(kBlock) void k_ray(Geo G, RayArgs A) {
 #pragma unroll
                 for (int ch = 0; ch < 3; ++ch) A.rout[3 * p.ray + ch] = H[ch];
             }
-        } else if constexpr (MODE == M_JVP) {
+        }
+    } else if constexpr (MODE == M_JVP) {
+        if (p.active) {
 #pragma unroll
             for (int ch = 0; ch < 3; ++ch) A.rout[3 * p.ray + ch] = Hd[ch];
-        } else if constexpr (MODE == M_VJP) {
-            const float u[3] = {A.uin[3 * p.ray], A.uin[3 * p.ray + 1], A.uin[3 * p.ray + 2]};
-            adjoint_scatter<PD>(G, r, X, u, depth, A.y);
-        } else if constexpr (MODE == M_JTJ) {
-            adjoint_scatter<PD>(G, r, X, Hd, depth, A.y);
-        } else if constexpr (MODE == M_GRAD) {
-            float res[3];
-#pragma unroll
-            for (int ch = 0; ch < 3; ++ch) {
-                res[ch] = H[ch] - A.targets[3 * p.ray + ch];
-                rr_sum += (double)res[ch] * (double)res[ch];
+        }
+    } else if constexpr (SCATTER) {
+        TexTable<NCH> TT;
+        TT.init(s_keys + wave * 64, s_tab + wave * NCH * 64);
+        if constexpr (JT) {
+            Brick4 B;
+            B.init(s_brick4 + wave * kB3, s_tag + wave * kB3);
+            float u[3] = {0.0f, 0.0f, 0.0f};
+            if (p.active) {
+                if constexpr (MODE == M_VJP) {
+                    u[0] = A.uin[3 * p.ray];
+                    u[1] = A.uin[3 * p.ray + 1];
+                    u[2] = A.uin[3 * p.ray + 2];
+                } else {
+                    u[0] = Hd[0];
+                    u[1] = Hd[1];
+                    u[2] = Hd[2];
+                }
             }
-            grad_scatter<PD>(G, r, X, res, depth, A.y, A.blocks);
-        } else if constexpr (MODE == M_FEAT) {
-            feature_scatter<PD>(G, r, X, H, Texit, A.y);
+            adjoint_scatter<PD>(G, r, p.active, X, u, depth, B, TT, A.y);
+        } else if constexpr (MODE == M_GRAD) {
+            Brick<NCH> B;
+            B.init(s_brick + wave * NCH * kB3);
+            float res[3] = {0.0f, 0.0f, 0.0f};
+            if (p.active) {
+#pragma unroll
+                for (int ch = 0; ch < 3; ++ch) {
+                    res[ch] = H[ch] - A.targets[3 * p.ray + ch];
+                    rr_sum += (double)res[ch] * (double)res[ch];
+                }
+            }
+            grad_scatter<PD>(G, r, p.active, X, res, depth, B, TT, A.y, A.blocks);
+        } else {
+            Brick<NCH> B;
+            B.init(s_brick + wave * NCH * kB3);
+            feature_scatter<PD>(G, r, p.active, X, depth, B, TT, A.y);
         }
     }
     if constexpr (MODE == M_RENDER || MODE == M_GRAD) {

@@ -323,6 +323,7 @@ __global__ void k_features(const float4* __restrict__ x, const float* __restrict
         const float* b = blocks + 5 * u;
         const float w = s[0];
         const float iw = w > 0.0f ? 1.0f / w : 0.0f;
+        const float iwt = s[1] > 0.0f ? 1.0f / s[1] : 0.0f;
         float* f = feat + 12 * u;
         f[0] = xv.w;
         f[1] = xv.x;
@@ -332,9 +333,9 @@ __global__ void k_features(const float4* __restrict__ x, const float* __restrict
         f[5] = logf(fmaxf(b[4], 0.0f) + 1e-12f);
         f[6] = log1pf(w);
         f[7] = s[1] * iw;
-        f[8] = s[2] * iw;
-        f[9] = s[3] * iw;
-        f[10] = s[4] * iw;
+        f[8] = s[2] * iwt;  // colour behind, unattenuated: sum w G / sum w T
+        f[9] = s[3] * iwt;
+        f[10] = s[4] * iwt;
         f[11] = s[5] * iw;
     }
 }
