@@ -193,6 +193,21 @@ __device__ __forceinline__ bool env_hit(const Geo& G, const Ray& r, int l, float
 
 __device__ __forceinline__ void atomic_add(float* p, float v) { unsafeAtomicAdd(p, v); }
 
+// exp(-t) from the hardware base-2 exponential, 2^(-t log2 e): v_exp_f32 is accurate to
+// about an ulp of its result, and rounding t log2 e moves the exponent by at most t ulp,
+// so the relative error stays near (1 + t) * 6e-8.
+__device__ __forceinline__ float exp_neg(float t) { return __builtin_amdgcn_exp2f(-t * 1.4426950408889634f); }
+
+// alpha = 1 - exp(-t) given e = exp(-t).  For |t| < 1/4 the difference 1 - e cancels, so
+// the truncated series t (1 - t/2 + t^2/6 - t^3/24 + t^4/120 - t^5/720) is used instead
+// (truncation error below t^6/5040 relative, 5e-8 at t = 1/4); above it 1 - e loses at most
+// a factor e/(1-e) < 3.6 on the relative error of e.
+__device__ __forceinline__ float one_minus_exp_neg(float t, float e) {
+    const float series =
+        t * (1.0f - t * (0.5f - t * (0.16666667f - t * (0.041666668f - t * (0.008333334f - t * 0.0013888889f)))));
+    return fabsf(t) < 0.25f ? series : 1.0f - e;
+}
+
 // ------------------------------------------------------------------ wave helpers
 __device__ __forceinline__ int wave_min_i(int v) {
 #pragma unroll
@@ -241,6 +256,7 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 typedef LDS f4 lds_f4;
 typedef LDS float lds_float;
 typedef LDS int lds_int;
+typedef LDS unsigned char lds_u8;
 
 __device__ __forceinline__ int ring_slot(int x, int y, int z) {
     return ((z & (kB - 1)) * kB + (y & (kB - 1))) * kB + (x & (kB - 1));
@@ -316,12 +332,12 @@ struct Window {
 // mostly target different voxels in the same round.
 struct Brick4 {
     Window win;
-    volatile lds_f4* s;    // [kB3]
-    volatile lds_int* tag; // [kB3]
+    volatile lds_f4* s;   // [kB3]
+    volatile lds_u8* tag; // [kB3] lane ids
 
-    __device__ __forceinline__ void init(f4* sb, int* tb) {
+    __device__ __forceinline__ void init(f4* sb, unsigned char* tb) {
         s = (volatile lds_f4*)sb;
-        tag = (volatile lds_int*)tb;
+        tag = (volatile lds_u8*)tb;
         win.o[0] = win.o[1] = win.o[2] = -(1 << 24);
         for (int i = lane_id(); i < kB3; i += 64) s[i] = f4{0.0f, 0.0f, 0.0f, 0.0f};
     }
@@ -349,19 +365,34 @@ struct Brick4 {
     // add val * weight(corner) to the 8 corners of every lane that is on (uniform call)
     template <class Sink>
     __device__ __forceinline__ void scatter8(const Geo& G, bool on, bool inb, const Corners& c, f4 val, Sink& out) {
-        const int lane = lane_id();
+        if (wave_any(on && !inb)) {  // corners outside the window: straight to HBM
+            if (on && !inb) {
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const int x = c.i[0] + (i & 1), y = c.i[1] + ((i >> 1) & 1), z = c.i[2] + (i >> 2);
+                    const f4 add = val * c.w[i];
+                    const float vv[4] = {add.x, add.y, add.z, add.w};
+                    out((z * G.ny + y) * G.nx + x, vv);
+                }
+            }
+        }
+        const bool mine = on && inb;
+        if (!wave_any(mine)) return;
+        const unsigned char lane = (unsigned char)lane_id();
         const int phi = ((lane & 7) + 3 * (lane >> 3)) & 7;
+        // ring-slot parts and axis weights of the two corners along each axis
+        const int sx0 = c.i[0] & 7, sx1 = (c.i[0] + 1) & 7;
+        const int sy0 = (c.i[1] & 7) << 3, sy1 = ((c.i[1] + 1) & 7) << 3;
+        const int sz0 = (c.i[2] & 7) << 6, sz1 = ((c.i[2] + 1) & 7) << 6;
+        const float wx0 = 1.0f - c.f[0], wy0 = 1.0f - c.f[1], wz0 = 1.0f - c.f[2];
 #pragma unroll 1
         for (int r = 0; r < 8; ++r) {
             const int i = (r + phi) & 7;
-            const int x = c.i[0] + (i & 1), y = c.i[1] + ((i >> 1) & 1), z = c.i[2] + (i >> 2);
-            const f4 add = val * corner_weight(c, i);
-            if (on && !inb) {
-                const float vv[4] = {add.x, add.y, add.z, add.w};
-                out((z * G.ny + y) * G.nx + x, vv);
-            }
-            bool pend = on && inb;
-            const int sl = ring_slot(x, y, z);
+            const bool bx = i & 1, by = i & 2, bz = i & 4;
+            const int sl = (bz ? sz1 : sz0) + (by ? sy1 : sy0) + (bx ? sx1 : sx0);
+            const float w = (bx ? c.f[0] : wx0) * (by ? c.f[1] : wy0) * (bz ? c.f[2] : wz0);
+            const f4 add = val * w;
+            bool pend = mine;
             while (wave_any(pend)) {
                 if (pend) tag[sl] = lane;
                 if (pend && tag[sl] == lane) {
@@ -566,8 +597,8 @@ __device__ __forceinline__ void forward(const Geo& G, const Ray& r, bool live, X
         }
         const float tau = sg * dk;
         depth.add(tau);
-        const float e = expf(-tau);
-        const float al = -expm1f(-tau);
+        const float e = exp_neg(tau);
+        const float al = one_minus_exp_neg(tau, e);
         const float Ta = T * al;
         H[0] += Ta * c0;
         H[1] += Ta * c1;
@@ -686,7 +717,7 @@ template <int PD>
 __device__ __forceinline__ void adjoint_scatter(const Geo& G, const Ray& r, bool live, XL<PD> X, const float u[3],
                                                 Depth depth, Brick4& B, TexTable<4>& TT, float* __restrict__ y) {
     SinkY sink{y};
-    const float Tx = expf(-depth.value());
+    const float Tx = exp_neg(depth.value());
     float uE = 0.0f;
     if (live) {
         float S[3];
@@ -737,8 +768,8 @@ __device__ __forceinline__ void adjoint_scatter(const Geo& G, const Ray& r, bool
             gather<PD>(X, c, nx, nxy, sg, c0, c1, c2);
             const float tau = sg * dk;
             depth.add(-tau);
-            const float T = (k == 0) ? 1.0f : expf(-depth.value());
-            const float al = -expm1f(-tau);
+            const float T = (k == 0) ? 1.0f : exp_neg(depth.value());
+            const float al = one_minus_exp_neg(tau, exp_neg(tau));
             const float A = T * al;
             const float uc = u[0] * c0 + u[1] * c1 + u[2] * c2;
             const float ds = dk * (Tn * uc - uG);
@@ -821,7 +852,7 @@ __device__ __forceinline__ void grad_scatter(const Geo& G, const Ray& r, bool li
                                              float* __restrict__ blocks) {
     SinkGrad sink{grad, blocks};
     GradOut out{G, B, sink, {rr[0], rr[1], rr[2]}};
-    const float Tx = expf(-depth.value());
+    const float Tx = exp_neg(depth.value());
     float S[3] = {0.0f, 0.0f, 0.0f};
     if (live) {
         // environment layers (the four texels of one lookup are distinct units)
@@ -890,8 +921,8 @@ __device__ __forceinline__ void grad_scatter(const Geo& G, const Ray& r, bool li
         gather<PD>(X, c, nx, nxy, sg, c0, c1, c2);
         const float tau = sg * dk;
         depth.add(-tau);
-        const float T = (k == 0) ? 1.0f : expf(-depth.value());
-        const float al = -expm1f(-tau);
+        const float T = (k == 0) ? 1.0f : exp_neg(depth.value());
+        const float al = one_minus_exp_neg(tau, exp_neg(tau));
         const float A = T * al;
         const float ds0 = dk * (Tn * c0 - G0);
         const float ds1 = dk * (Tn * c1 - G1);
@@ -922,7 +953,7 @@ template <int PD>
 __device__ __forceinline__ void feature_scatter(const Geo& G, const Ray& r, bool live, XL<PD> X, Depth depth,
                                                 Brick<6>& B, TexTable<6>& TT, float* __restrict__ sums) {
     SinkFeat sink{sums};
-    const float Tx = expf(-depth.value());
+    const float Tx = exp_neg(depth.value());
     float S[3] = {0.0f, 0.0f, 0.0f};
     if (live) {
         auto emit = [&](const Tex& tx, const float c[3], float al, float Tl, const float Sb[3]) {
@@ -966,8 +997,8 @@ __device__ __forceinline__ void feature_scatter(const Geo& G, const Ray& r, bool
         gather<PD>(X, c, nx, nxy, sg, c0, c1, c2);
         const float tau = sg * dk;
         depth.add(-tau);
-        const float T = (k == 0) ? 1.0f : expf(-depth.value());
-        const float al = -expm1f(-tau);
+        const float T = (k == 0) ? 1.0f : exp_neg(depth.value());
+        const float al = one_minus_exp_neg(tau, exp_neg(tau));
         const float A = T * al;
         const bool inb = B.inside(lo, hi);
 #pragma unroll
@@ -1040,7 +1071,7 @@ __global__ __launch_bounds__(kBlock) void k_ray(Geo G, RayArgs A) {
     constexpr bool JT = MODE == M_VJP || MODE == M_JTJ;
     __shared__ float s_brick[(SCATTER && !JT) ? kWaves * NCH * kB3 : 1];
     __shared__ f4 s_brick4[JT ? kWaves * kB3 : 1];
-    __shared__ int s_tag[JT ? kWaves * kB3 : 1];
+    __shared__ unsigned char s_tag[JT ? kWaves * kB3 : 1];
     __shared__ float s_tab[SCATTER ? kWaves * NCH * 64 : 1];
     __shared__ int s_keys[SCATTER ? kWaves * 64 : 1];
     if (A.done && *A.done) return;
