@@ -75,6 +75,7 @@ def _load():
         lib.orc_sample_field.restype = ctypes.c_double
         lib.orc_sample_field.argtypes = [P, P, P, ctypes.c_int]
         lib.orc_ray.argtypes = [P, i64, P, P]
+        lib.orc_feature_sums.argtypes = [P, P, P, i64, P]
         lib.orc_num_threads.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -226,6 +227,14 @@ class OracleScene:
         x = _f64(x)
         p = _f64(p)
         return float(self.lib.orc_sample_field(self.p, _ptr(x), _ptr(p), int(ch)))
+
+    def feature_sums(self, x, rays=None):
+        """[units, 6] sums (w, wT, wG (3), w alpha) over every sample corner / texel."""
+        x = _f64(x)
+        r_ids, n = self._rays(rays)
+        out = np.zeros((self.n_units, 6))
+        self.lib.orc_feature_sums(self.p, _ptr(x), _ptr(r_ids), n, _ptr(out))
+        return out
 
     def num_threads(self) -> int:
         return int(self.lib.orc_num_threads())

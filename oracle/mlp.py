@@ -1,0 +1,195 @@
+"""FP64 reference of the learned block preconditioner (test infrastructure only).
+
+Not part of the paper: the learned part replaces the exact inverse of each unit's
+4x4 block of J^T J (Sec. III-G uses only its diagonal) with a prediction from cheap
+per-unit features.  Conventions, identical to the product's:
+
+  weights, packed: W1[64][16] b1[64] W2[64][64] b2[64] W3[16][64] b3[16]
+                   (inputs padded 12 -> 16, outputs 10 -> 16 with zeros)
+  network:         h1 = relu(W1 x + b1), h2 = relu(W2 h1 + b2), o = W3 h2 + b3
+  factor:          L lower triangular from o[0:10] row by row, softplus on the diagonal
+  ridge:           rho = 1e-6 max(d, f); D = diag(d, d, d, f) + rho I
+  normalised block B~ = D^-1/2 (B + rho I) D^-1/2,  M^-1 = D^-1/2 L L^T D^-1/2
+  loss per unit:   || L L^T B~ - I ||_F^2, averaged over all n units given (a unit
+                   no ray touches contributes zero)
+"""
+from __future__ import annotations
+
+import numpy as np
+
+N_IN, N_IN_PAD, N_HID, N_OUT, N_OUT_PAD = 12, 16, 64, 10, 16
+SHAPES = [("W1", (N_HID, N_IN_PAD)), ("b1", (N_HID,)), ("W2", (N_HID, N_HID)), ("b2", (N_HID,)),
+          ("W3", (N_OUT_PAD, N_HID)), ("b3", (N_OUT_PAD,))]
+NW = sum(int(np.prod(s)) for _, s in SHAPES)
+TRIL = [(0, 0), (1, 0), (1, 1), (2, 0), (2, 1), (2, 2), (3, 0), (3, 1), (3, 2), (3, 3)]
+DIAG = [0, 2, 5, 9]
+RIDGE = 1e-6
+
+
+def bf16_round(w: np.ndarray) -> np.ndarray:
+    """Round float values to bfloat16 (nearest even) and return them as float64."""
+    f = np.asarray(w, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) & 0xFFFF
+    return (r.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+
+
+def bf16_bits(w: np.ndarray) -> np.ndarray:
+    f = np.asarray(w, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    return (((u + 0x7FFF + ((u >> 16) & 1)) >> 16) & 0xFFFF).astype(np.uint16)
+
+
+def bits_to_f64(b: np.ndarray) -> np.ndarray:
+    return (np.asarray(b, dtype=np.uint32) << 16).view(np.float32).astype(np.float64)
+
+
+def unpack(w: np.ndarray) -> dict:
+    w = np.asarray(w, dtype=np.float64).reshape(-1)
+    assert w.size == NW
+    out, o = {}, 0
+    for name, shape in SHAPES:
+        n = int(np.prod(shape))
+        out[name] = w[o:o + n].reshape(shape)
+        o += n
+    return out
+
+
+def pack(p: dict) -> np.ndarray:
+    return np.concatenate([np.asarray(p[name], dtype=np.float64).reshape(-1) for name, _ in SHAPES])
+
+
+def init_weights(seed: int = 0) -> np.ndarray:
+    """He-style initialisation; padded input columns and output rows are zero."""
+    rng = np.random.default_rng(seed)
+    p = {"W1": rng.normal(0, np.sqrt(2.0 / N_IN), (N_HID, N_IN_PAD)), "b1": np.zeros(N_HID),
+         "W2": rng.normal(0, np.sqrt(2.0 / N_HID), (N_HID, N_HID)), "b2": np.zeros(N_HID),
+         "W3": rng.normal(0, np.sqrt(1.0 / N_HID), (N_OUT_PAD, N_HID)), "b3": np.zeros(N_OUT_PAD)}
+    p["W1"][:, N_IN:] = 0.0
+    p["W3"][N_OUT:, :] = 0.0
+    p["W3"] *= 0.1
+    p["b3"][DIAG] = 0.5413  # softplus(0.5413) = 1: start at L = I, i.e. plain Jacobi
+    return pack(p)
+
+
+def features(x: np.ndarray, sums: np.ndarray, blocks: np.ndarray) -> np.ndarray:
+    """[units, 12]: sigma/alpha, colour (3), log d, log f, log(1 + sum w), mean T,
+    colour behind (sum w G / sum w T, 3), mean alpha."""
+    x = np.asarray(x, dtype=np.float64).reshape(-1, 4)
+    s = np.asarray(sums, dtype=np.float64)
+    b = np.asarray(blocks, dtype=np.float64)
+    f = np.zeros((x.shape[0], N_IN))
+    w, wt = s[:, 0], s[:, 1]
+    iw = np.where(w > 0, 1.0 / np.where(w > 0, w, 1.0), 0.0)
+    iwt = np.where(wt > 0, 1.0 / np.where(wt > 0, wt, 1.0), 0.0)
+    f[:, 0] = x[:, 3]
+    f[:, 1:4] = x[:, 0:3]
+    f[:, 4] = np.log(np.maximum(b[:, 0], 0.0) + 1e-12)
+    f[:, 5] = np.log(np.maximum(b[:, 4], 0.0) + 1e-12)
+    f[:, 6] = np.log1p(w)
+    f[:, 7] = wt * iw
+    f[:, 8:11] = s[:, 2:5] * iwt[:, None]
+    f[:, 11] = s[:, 5] * iw
+    return f
+
+
+def forward(w: np.ndarray, feat: np.ndarray, emulate_bf16: bool = False):
+    """Raw outputs [n, 10] and the activations needed for the backward pass.
+
+    emulate_bf16 rounds the input and both hidden activations to bfloat16 before the
+    next product, as a bfloat16 matrix-core implementation does (products and sums
+    stay exact here)."""
+    p = unpack(w)
+    rnd = bf16_round if emulate_bf16 else (lambda a: a)
+    x = np.zeros((feat.shape[0], N_IN_PAD))
+    x[:, :N_IN] = feat
+    x = rnd(x)
+    z1 = x @ p["W1"].T + p["b1"]
+    h1 = rnd(np.maximum(z1, 0.0))
+    z2 = h1 @ p["W2"].T + p["b2"]
+    h2 = rnd(np.maximum(z2, 0.0))
+    o = h2 @ p["W3"].T + p["b3"]
+    return o[:, :N_OUT], (x, z1, h1, z2, h2)
+
+
+def softplus(v):
+    return np.logaddexp(0.0, v)
+
+
+def factor(raw: np.ndarray) -> np.ndarray:
+    """[n, 4, 4] lower-triangular L with softplus on the diagonal."""
+    L = np.zeros((raw.shape[0], 4, 4))
+    for k, (i, j) in enumerate(TRIL):
+        L[:, i, j] = softplus(raw[:, k]) if k in DIAG else raw[:, k]
+    return L
+
+
+def normalised_block(blocks: np.ndarray):
+    """(B~ [n,4,4], D^-1/2 [n,4], live mask)."""
+    b = np.asarray(blocks, dtype=np.float64)
+    d, e, f = b[:, 0], b[:, 1:4], b[:, 4]
+    m = np.maximum(d, f)
+    live = m > 0
+    rho = RIDGE * m
+    dd, ff = d + rho, f + rho
+    sd = np.where(live, 1.0 / np.sqrt(np.where(live, dd, 1.0)), 0.0)
+    sf = np.where(live, 1.0 / np.sqrt(np.where(live, ff, 1.0)), 0.0)
+    Bn = np.zeros((b.shape[0], 4, 4))
+    for i in range(3):
+        Bn[:, i, i] = np.where(live, 1.0, 0.0)
+        Bn[:, i, 3] = e[:, i] * sd * sf
+        Bn[:, 3, i] = e[:, i] * sd * sf
+    Bn[:, 3, 3] = np.where(live, 1.0, 0.0)
+    dis = np.stack([sd, sd, sd, sf], axis=1)
+    return Bn, dis, live
+
+
+def minv(w: np.ndarray, feat: np.ndarray, blocks: np.ndarray, emulate_bf16: bool = False) -> np.ndarray:
+    """[n, 4, 4] M^-1 = D^-1/2 L L^T D^-1/2 (zero for units with no rays)."""
+    raw, _ = forward(w, feat, emulate_bf16)
+    L = factor(raw)
+    _, dis, live = normalised_block(blocks)
+    P = L @ np.transpose(L, (0, 2, 1))
+    M = dis[:, :, None] * P * dis[:, None, :]
+    M[~live] = 0.0
+    return M
+
+
+def loss_and_grad(w: np.ndarray, feat: np.ndarray, blocks: np.ndarray):
+    """Mean over the n given units of ||L L^T B~ - I||_F^2 (zero for units no ray touches)
+    and its gradient w.r.t. the packed weights."""
+    p = unpack(w)
+    raw, (x, z1, h1, z2, h2) = forward(w, feat)
+    L = factor(raw)
+    Bn, _, live = normalised_block(blocks)
+    n_live = max(int(raw.shape[0]), 1)
+    P = L @ np.transpose(L, (0, 2, 1))
+    E = P @ Bn - np.eye(4)[None]
+    E[~live] = 0.0
+    loss = float((E * E).sum()) / n_live
+    G = 2.0 * E @ Bn / n_live                      # d loss / d P
+    dL = (G + np.transpose(G, (0, 2, 1))) @ L      # d loss / d L
+    draw = np.zeros_like(raw)
+    for k, (i, j) in enumerate(TRIL):
+        draw[:, k] = dL[:, i, j] * (1.0 / (1.0 + np.exp(-raw[:, k])) if k in DIAG else 1.0)
+    do = np.zeros((raw.shape[0], N_OUT_PAD))
+    do[:, :N_OUT] = draw
+    g = {"W3": do.T @ h2, "b3": do.sum(0)}
+    dh2 = do @ p["W3"]
+    dz2 = dh2 * (z2 > 0)
+    g["W2"] = dz2.T @ h1
+    g["b2"] = dz2.sum(0)
+    dh1 = dz2 @ p["W2"]
+    dz1 = dh1 * (z1 > 0)
+    g["W1"] = dz1.T @ x
+    g["b1"] = dz1.sum(0)
+    return loss, pack(g)
+
+
+def raw_from_factor(L: np.ndarray) -> np.ndarray:
+    """Inverse of `factor`: raw outputs that reproduce a given L (positive diagonal)."""
+    raw = np.zeros((L.shape[0], N_OUT))
+    for k, (i, j) in enumerate(TRIL):
+        v = L[:, i, j]
+        raw[:, k] = np.log(np.expm1(v)) if k in DIAG else v
+    return raw

@@ -381,7 +381,59 @@ int32_t perf_objective(perf_scene* s, const float* d_x, const float* d_delta, fl
     return read_scalar(s, S_TMP, F_host);
 }
 
-int32_t perf_precond_learned_minv(perf_scene* s, const void* xg, const float* x32);
+
+// ---------------------------------------------------------------- learned block preconditioner
+static int32_t features_pass(perf_scene* s, const void* xg, const void* xvals, int xdtype, float* feat,
+                             const float* blocks) {
+    CK(launch_zero(s->featsum, 6 * s->units, s->stream));
+    CK(launch_features(s->desc.param_dtype, s->geo, s->cams, xg, s->featsum, s->stream));
+    CK(launch_features_finalize(xvals, xdtype, s->featsum, blocks, s->units, feat, s->stream));
+    return PERF_OK;
+}
+
+int32_t perf_precond_features(perf_scene* s, const void* d_x, float* d_feat, float* d_blocks) {
+    if (!s || !d_x || !d_feat) return fail(PERF_EINVAL, "null argument");
+    if (!s->featsum) return fail(PERF_EUNSUPPORTED, "the scene was created without learned = 1");
+    float* blocks = d_blocks ? d_blocks : s->blocks;
+    int32_t rc = grad_pass(s, d_x, nullptr, blocks, false);
+    if (rc != PERF_OK) return rc;
+    return features_pass(s, d_x, d_x, s->desc.param_dtype, d_feat, blocks);
+}
+
+int32_t perf_mlp_set_weights(perf_scene* s, const uint16_t* d_w, int32_t n_w) {
+    if (!s || !d_w) return fail(PERF_EINVAL, "null argument");
+    if (!s->mlpw) return fail(PERF_EUNSUPPORTED, "the scene was created without learned = 1");
+    if (n_w != PERF_MLP_NW) return fail(PERF_EINVAL, "expected %d weights, got %d", PERF_MLP_NW, n_w);
+    CK(hipMemcpyAsync(s->mlpw, d_w, sizeof(uint16_t) * PERF_MLP_NW, hipMemcpyDeviceToDevice, s->stream));
+    s->mlp_ready = true;
+    return PERF_OK;
+}
+
+int32_t perf_mlp_infer(perf_scene* s, const float* d_feat, const float* d_blocks, float* d_minv) {
+    if (!s || !d_feat || !d_blocks || !d_minv) return fail(PERF_EINVAL, "null argument");
+    if (!s->mlp_ready) return fail(PERF_EINVAL, "no weights (perf_mlp_set_weights)");
+    CK(launch_mlp_infer(s->mlpw, d_feat, d_blocks, s->units, d_minv, s->stream));
+    return PERF_OK;
+}
+
+int32_t perf_mlp_train_step(float* d_w32, uint16_t* d_wbf16, float* d_m, float* d_v, int32_t t, float lr,
+                            const float* d_feat, const float* d_blocks, int32_t n, float* d_loss, float* d_grad_scratch,
+                            void* stream) {
+    if (!d_w32 || !d_wbf16 || !d_m || !d_v || !d_loss || !d_grad_scratch) return fail(PERF_EINVAL, "null argument");
+    if (n < 0 || (n > 0 && (!d_feat || !d_blocks))) return fail(PERF_EINVAL, "bad batch");
+    if (t < 1 || !(lr > 0.0f)) return fail(PERF_EINVAL, "need t >= 1 and lr > 0");
+    CK(launch_mlp_train(d_w32, d_wbf16, d_m, d_v, t, lr, d_feat, d_blocks, n, d_loss, d_grad_scratch,
+                        (hipStream_t)stream));
+    return PERF_OK;
+}
+
+// features at x (the blocks of this step are already in s->blocks) and the predicted inverses
+static int32_t learned_minv(perf_scene* s, const void* xg, const float* x32) {
+    int32_t rc = features_pass(s, xg, x32, PERF_F32, s->feat, s->blocks);
+    if (rc != PERF_OK) return rc;
+    CK(launch_mlp_infer(s->mlpw, s->feat, s->blocks, s->units, s->minv, s->stream));
+    return PERF_OK;
+}
 
 int32_t perf_gn_step(perf_scene* s, float* d_x, const perf_pcg_opts* opts, perf_gn_stats* stats) {
     if (!s || !d_x || !opts) return fail(PERF_EINVAL, "null argument");
@@ -432,7 +484,7 @@ int32_t perf_gn_step(perf_scene* s, float* d_x, const perf_pcg_opts* opts, perf_
     if (kind == PERF_PRECOND_JACOBI || kind == PERF_PRECOND_BLOCK4) {
         CK(launch_precond_invert(kind, s->blocks, s->units, s->minv, st));
     } else if (kind == PERF_PRECOND_LEARNED) {
-        rc = perf_precond_learned_minv(s, xg, d_x);
+        rc = learned_minv(s, xg, d_x);
         if (rc != PERF_OK) return rc;
         apply_kind = PERF_PRECOND_BLOCK4;
     }

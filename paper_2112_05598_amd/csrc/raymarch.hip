@@ -1139,7 +1139,7 @@ __global__ __launch_bounds__(kBlock) void k_ray(Geo G, RayArgs A) {
             Brick<NCH> B;
             B.init(s_brick + wave * NCH * kB3);
             float res[3] = {0.0f, 0.0f, 0.0f};
-            if (p.active) {
+            if (p.active && A.targets) {
 #pragma unroll
                 for (int ch = 0; ch < 3; ++ch) {
                     res[ch] = H[ch] - A.targets[3 * p.ray + ch];

@@ -315,10 +315,18 @@ __global__ void k_check_finite(const float* __restrict__ p, int64_t n, int* flag
 }
 
 // features [units][12] from the parameters, the per-unit sums and the blocks
-__global__ void k_features(const float4* __restrict__ x, const float* __restrict__ sums,
+__device__ __forceinline__ float bf16f(unsigned short b) { return __uint_as_float(((unsigned)b) << 16); }
+
+__global__ void k_features(const void* __restrict__ xp, int x_bf16, const float* __restrict__ sums,
                            const float* __restrict__ blocks, int64_t units, float* __restrict__ feat) {
     for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < units; u += (int64_t)gridDim.x * blockDim.x) {
-        const float4 xv = x[u];
+        float4 xv;
+        if (x_bf16) {
+            const ushort4 q = reinterpret_cast<const ushort4*>(xp)[u];
+            xv = make_float4(bf16f(q.x), bf16f(q.y), bf16f(q.z), bf16f(q.w));
+        } else {
+            xv = reinterpret_cast<const float4*>(xp)[u];
+        }
         const float* s = sums + 6 * u;
         const float* b = blocks + 5 * u;
         const float w = s[0];
@@ -460,9 +468,9 @@ hipError_t launch_check_finite(const float* p, int64_t n, int* flag, hipStream_t
     return hipGetLastError();
 }
 
-hipError_t launch_features_finalize(const float* x, const float* sums, const float* blocks, int64_t units, float* feat,
-                                    hipStream_t st) {
-    hipLaunchKernelGGL(k_features, dim3(grid_for(units)), dim3(kVecBlock), 0, st, reinterpret_cast<const float4*>(x),
+hipError_t launch_features_finalize(const void* x, int x_dtype, const float* sums, const float* blocks,
+                                    int64_t units, float* feat, hipStream_t st) {
+    hipLaunchKernelGGL(k_features, dim3(grid_for(units)), dim3(kVecBlock), 0, st, x, x_dtype == PERF_BF16 ? 1 : 0,
                        sums, blocks, units, feat);
     return hipGetLastError();
 }

@@ -175,6 +175,31 @@ class Scene:
         abi.check(self.lib.perf_footprint(self.handle, _ptr(pr), _ptr(tot)))
         return (pr.view(-1, 2) if pr is not None else None), tot
 
+    # ------------------------------------------------------------ learned preconditioner
+    def features(self, x):
+        """(features [units, 12], exact blocks [units, 5]) at x."""
+        self._check_params(x)
+        self._bind()
+        feat = torch.empty(self.n_units * 12, dtype=torch.float32, device=self.device)
+        blocks = torch.empty(self.n_units * 5, dtype=torch.float32, device=self.device)
+        abi.check(self.lib.perf_precond_features(self.handle, _ptr(x), _ptr(feat), _ptr(blocks)))
+        return feat.view(-1, 12), blocks.view(-1, 5)
+
+    def mlp_set_weights(self, w_bf16: torch.Tensor):
+        if w_bf16.dtype != torch.bfloat16 or w_bf16.numel() != abi.PERF_MLP_NW or w_bf16.device != self.device:
+            raise ValueError("weights must be a bfloat16 tensor of PERF_MLP_NW elements on the scene's device")
+        self._bind()
+        self._mlp_w = w_bf16.contiguous()
+        abi.check(self.lib.perf_mlp_set_weights(self.handle, _ptr(self._mlp_w), abi.PERF_MLP_NW))
+
+    def mlp_infer(self, feat: torch.Tensor, blocks: torch.Tensor):
+        """[units, 10] upper triangles of the predicted block inverses."""
+        self._bind()
+        out = torch.empty(self.n_units * 10, dtype=torch.float32, device=self.device)
+        abi.check(self.lib.perf_mlp_infer(self.handle, _ptr(feat.contiguous()), _ptr(blocks.contiguous()),
+                                          _ptr(out)))
+        return out.view(-1, 10)
+
     def gn_step(self, x: torch.Tensor, max_iters: int = 20, precond: str = "jacobi", rel_tol: float = 0.0,
                 abs_eps: float = 0.0, stall_ratio: float = 0.0, line_search: bool = True, ls_factor: float = 0.7,
                 ls_max: int = 20) -> dict:
@@ -191,3 +216,12 @@ class Scene:
         return dict(F_before=st.F_before, F_after=st.F_after, gamma=st.gamma, pcg_iters=k, ls_trials=st.ls_trials,
                     flags=st.flags, R0=st.R0, R=list(st.R[:k]), alpha=list(st.alpha[:k]),
                     beta=list(st.beta[:max(k - 1, 0)]), pAp=list(st.pAp[:k + 1]), ms_phase=list(st.ms_phase[:6]), ms_jtj=st.ms_phase[6], n_jtj=int(st.ms_phase[7]))
+
+
+def mlp_train_step(w32, wbf16, m, v, t: int, lr: float, feat, blocks, loss, grad, stream=None):
+    """One Adam step of the learned preconditioner on a batch (feat [n,12], blocks [n,5])."""
+    lib = abi.load()
+    n = int(feat.shape[0])
+    st = ctypes.c_void_p(torch.cuda.current_stream(feat.device).cuda_stream) if stream is None else stream
+    abi.check(lib.perf_mlp_train_step(_ptr(w32), _ptr(wbf16), _ptr(m), _ptr(v), int(t), ctypes.c_float(lr),
+                                      _ptr(feat), _ptr(blocks), n, _ptr(loss), _ptr(grad), st))
