@@ -225,8 +225,11 @@ int32_t perf_pack_bf16(const float* d_in, uint16_t* d_out, int64_t n, void* stre
  * perf_mlp_infer: d_minv [units][10] from features and blocks: the network's output is a
  *   lower-triangular L (10 values, softplus on the diagonal); M^-1 = D^-1/2 L L^T D^-1/2 with
  *   D = diag(d, d, d, f); units with max(d, f) = 0 get 0.
- * perf_mlp_train_step: one Adam step on a batch of n (feature, block) rows: loss =
- *   mean ||L L^T Bn - I||_F^2 with Bn = D^-1/2 B D^-1/2; FP32 master weights d_w32 [PERF_MLP_NW],
+ * perf_mlp_train_step: one Adam step on a batch of n (feature, block) rows: per-unit error
+ *   E = L L^T (Bn + damp I) - I with Bn = D^-1/2 B D^-1/2, so that the target is the damped
+ *   normalised inverse (damp = 0: exact block-Jacobi; damp -> inf: Jacobi); the loss is the
+ *   mean over the n rows of q = ||E||_F^2 where q <= 4 and 4 sqrt(q) - 4 above (robust against
+ *   near-singular blocks); FP32 master weights d_w32 [PERF_MLP_NW],
  *   Adam moments d_m, d_v [PERF_MLP_NW], step count t (>= 1), learning rate lr; writes the
  *   updated bf16 copy to d_wbf16 and the batch loss to d_loss (device float[1]).
  */
@@ -235,7 +238,7 @@ int32_t perf_precond_features(perf_scene* s, const void* d_x, float* d_feat, flo
 int32_t perf_mlp_set_weights(perf_scene* s, const uint16_t* d_w, int32_t n_w);
 int32_t perf_mlp_infer(perf_scene* s, const float* d_feat, const float* d_blocks, float* d_minv);
 int32_t perf_mlp_train_step(float* d_w32, uint16_t* d_wbf16, float* d_m, float* d_v, int32_t t, float lr,
-                            const float* d_feat, const float* d_blocks, int32_t n, float* d_loss,
+                            float damp, const float* d_feat, const float* d_blocks, int32_t n, float* d_loss,
                             float* d_grad_scratch, void* stream);
 
 #ifdef __cplusplus

@@ -10,8 +10,10 @@ per-unit features.  Conventions, identical to the product's:
   factor:          L lower triangular from o[0:10] row by row, softplus on the diagonal
   ridge:           rho = 1e-6 max(d, f); D = diag(d, d, d, f) + rho I
   normalised block B~ = D^-1/2 (B + rho I) D^-1/2,  M^-1 = D^-1/2 L L^T D^-1/2
-  loss per unit:   || L L^T B~ - I ||_F^2, averaged over all n units given (a unit
-                   no ray touches contributes zero)
+  loss per unit:   q = || L L^T (B~ + damp I) - I ||_F^2 (damp = 0: the exact inverse is the
+                   target; larger damp moves it towards plain Jacobi), made robust above KAPPA:
+                   q if q <= KAPPA, else 2 sqrt(KAPPA q) - KAPPA (linear in the norm), averaged
+                   over all n units given (a unit no ray touches contributes zero)
 """
 from __future__ import annotations
 
@@ -24,6 +26,7 @@ NW = sum(int(np.prod(s)) for _, s in SHAPES)
 TRIL = [(0, 0), (1, 0), (1, 1), (2, 0), (2, 1), (2, 2), (3, 0), (3, 1), (3, 2), (3, 3)]
 DIAG = [0, 2, 5, 9]
 RIDGE = 1e-6
+KAPPA = 4.0
 
 
 def bf16_round(w: np.ndarray) -> np.ndarray:
@@ -155,19 +158,24 @@ def minv(w: np.ndarray, feat: np.ndarray, blocks: np.ndarray, emulate_bf16: bool
     return M
 
 
-def loss_and_grad(w: np.ndarray, feat: np.ndarray, blocks: np.ndarray):
-    """Mean over the n given units of ||L L^T B~ - I||_F^2 (zero for units no ray touches)
-    and its gradient w.r.t. the packed weights."""
+def loss_and_grad(w: np.ndarray, feat: np.ndarray, blocks: np.ndarray, damp: float = 0.0):
+    """Mean over the n given units of the robust ||L L^T (B~ + damp I) - I||_F^2 (zero for
+    units no ray touches) and its gradient w.r.t. the packed weights."""
     p = unpack(w)
     raw, (x, z1, h1, z2, h2) = forward(w, feat)
     L = factor(raw)
     Bn, _, live = normalised_block(blocks)
+    Bn = Bn + damp * np.where(live, 1.0, 0.0)[:, None, None] * np.eye(4)[None]
     n_live = max(int(raw.shape[0]), 1)
     P = L @ np.transpose(L, (0, 2, 1))
     E = P @ Bn - np.eye(4)[None]
     E[~live] = 0.0
-    loss = float((E * E).sum()) / n_live
-    G = 2.0 * E @ Bn / n_live                      # d loss / d P
+    q = (E * E).sum(axis=(1, 2))
+    big = q > KAPPA
+    lu = np.where(big, 2.0 * np.sqrt(KAPPA * np.where(big, q, 1.0)) - KAPPA, q)
+    scale = np.where(big, np.sqrt(KAPPA / np.where(big, q, 1.0)), 1.0)  # d lu / d q
+    loss = float(lu.sum()) / n_live
+    G = 2.0 * (scale[:, None, None] * E) @ Bn / n_live   # d loss / d P
     dL = (G + np.transpose(G, (0, 2, 1))) @ L      # d loss / d L
     draw = np.zeros_like(raw)
     for k, (i, j) in enumerate(TRIL):

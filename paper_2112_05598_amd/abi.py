@@ -95,7 +95,7 @@ SIGNATURES = [
     ("perf_precond_features", _I32, [_P, _P, _P, _P]),
     ("perf_mlp_set_weights", _I32, [_P, _P, _I32]),
     ("perf_mlp_infer", _I32, [_P, _P, _P, _P]),
-    ("perf_mlp_train_step", _I32, [_P, _P, _P, _P, _I32, ctypes.c_float, _P, _P, _I32, _P, _P, _P]),
+    ("perf_mlp_train_step", _I32, [_P, _P, _P, _P, _I32, ctypes.c_float, ctypes.c_float, _P, _P, _I32, _P, _P, _P]),
 ]
 
 _lib = None

@@ -417,12 +417,13 @@ int32_t perf_mlp_infer(perf_scene* s, const float* d_feat, const float* d_blocks
 }
 
 int32_t perf_mlp_train_step(float* d_w32, uint16_t* d_wbf16, float* d_m, float* d_v, int32_t t, float lr,
-                            const float* d_feat, const float* d_blocks, int32_t n, float* d_loss, float* d_grad_scratch,
+                            float damp, const float* d_feat, const float* d_blocks, int32_t n, float* d_loss, float* d_grad_scratch,
                             void* stream) {
     if (!d_w32 || !d_wbf16 || !d_m || !d_v || !d_loss || !d_grad_scratch) return fail(PERF_EINVAL, "null argument");
     if (n < 0 || (n > 0 && (!d_feat || !d_blocks))) return fail(PERF_EINVAL, "bad batch");
     if (t < 1 || !(lr > 0.0f)) return fail(PERF_EINVAL, "need t >= 1 and lr > 0");
-    CK(launch_mlp_train(d_w32, d_wbf16, d_m, d_v, t, lr, d_feat, d_blocks, n, d_loss, d_grad_scratch,
+    if (!(damp >= 0.0f && damp <= 1e6f)) return fail(PERF_EINVAL, "damp must be in [0, 1e6]");
+    CK(launch_mlp_train(d_w32, d_wbf16, d_m, d_v, t, lr, damp, d_feat, d_blocks, n, d_loss, d_grad_scratch,
                         (hipStream_t)stream));
     return PERF_OK;
 }

@@ -30,6 +30,7 @@ static_assert(NW == PERF_MLP_NW, "packed weight layout");
 constexpr int TU = 64;   // units per wave tile
 constexpr int LD16 = 20, LD32 = 36, LD64 = 68;  // padded row strides (elements)
 constexpr float kRidge = 1e-6f;
+constexpr float kKappa = 4.0f;  // per-unit loss is quadratic up to ||E||^2 = kKappa, linear in ||E|| above
 
 __device__ __forceinline__ unsigned short f2bf(float f) {
     const unsigned u = __float_as_uint(f);
@@ -244,7 +245,7 @@ __global__ __launch_bounds__(64 * kInferWaves) void k_mlp_infer(const unsigned s
 // One wave per workgroup (the activations of a tile are kept in both orientations).
 __global__ __launch_bounds__(64) void k_mlp_train(const unsigned short* __restrict__ w,
                                                   const float* __restrict__ feat, const float* __restrict__ blocks,
-                                                  int n, float inv_n, float* __restrict__ grad,
+                                                  int n, float inv_n, float damp, float* __restrict__ grad,
                                                   float* __restrict__ loss) {
     __shared__ unsigned short sW1[NH * LD16], sW2[NH * LD64], sW3[32 * LD64], sW2t[NH * LD64], sW3t[NH * LD32];
     __shared__ float sb1[NH], sb2[NH], sb3[NOP];
@@ -258,7 +259,7 @@ __global__ __launch_bounds__(64) void k_mlp_train(const unsigned short* __restri
     load_features(feat, unit, n, (lds_bf*)sX + l * LD16, (lds_bf*)sXt, l);
     forward_tile(W, (lds_bf*)sX, (lds_bf*)sH1, (lds_bf*)sH2, sO, (lds_bf*)sH1t, (lds_bf*)sH2t);
 
-    // loss ||L L^T B~ - I||_F^2 of this unit and its gradient w.r.t. the raw outputs
+    // robust loss of E = L L^T (B~ + damp I) - I for this unit and its gradient w.r.t. the raw outputs
     float dr[NO];
 #pragma unroll
     for (int i = 0; i < NO; ++i) dr[i] = 0.0f;
@@ -272,8 +273,9 @@ __global__ __launch_bounds__(64) void k_mlp_train(const unsigned short* __restri
             const float sd = 1.0f / sqrtf(d + rho), sf = 1.0f / sqrtf(f + rho);
             // normalised block D^-1/2 (B + rho I) D^-1/2: unit diagonal, e / sqrt(d f) off it
             const float e0 = b[1] * sd * sf, e1 = b[2] * sd * sf, e2 = b[3] * sd * sf;
-            const float Bn[4][4] = {{1.0f, 0.0f, 0.0f, e0}, {0.0f, 1.0f, 0.0f, e1}, {0.0f, 0.0f, 1.0f, e2},
-                                    {e0, e1, e2, 1.0f}};
+            const float g1 = 1.0f + damp;
+            const float Bn[4][4] = {{g1, 0.0f, 0.0f, e0}, {0.0f, g1, 0.0f, e1}, {0.0f, 0.0f, g1, e2},
+                                    {e0, e1, e2, g1}};
             float raw[NO];
 #pragma unroll
             for (int i = 0; i < NO; ++i) raw[i] = sO[l * 17 + i];
@@ -299,6 +301,11 @@ __global__ __launch_bounds__(64) void k_mlp_train(const unsigned short* __restri
                     E[i][j] = e;
                     lu += e * e;
                 }
+            float scale = 1.0f;  // d loss / d ||E||^2 of the robust per-unit loss
+            if (lu > kKappa) {
+                scale = sqrtf(kKappa / lu);
+                lu = 2.0f * sqrtf(kKappa * lu) - kKappa;
+            }
 #pragma unroll
             for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -306,7 +313,7 @@ __global__ __launch_bounds__(64) void k_mlp_train(const unsigned short* __restri
                     float g = 0.0f;
 #pragma unroll
                     for (int q = 0; q < 4; ++q) g += E[i][q] * Bn[q][j];
-                    G[i][j] = 2.0f * inv_n * g;
+                    G[i][j] = 2.0f * inv_n * scale * g;
                 }
             int k = 0;
 #pragma unroll
@@ -460,12 +467,12 @@ hipError_t launch_mlp_infer(const uint16_t* w, const float* feat, const float* b
     return hipGetLastError();
 }
 
-hipError_t launch_mlp_train(float* w32, uint16_t* wbf, float* m, float* v, int t, float lr, const float* feat,
+hipError_t launch_mlp_train(float* w32, uint16_t* wbf, float* m, float* v, int t, float lr, float damp, const float* feat,
                             const float* blocks, int n, float* loss, float* grad, hipStream_t st) {
     hipLaunchKernelGGL(k_zero1, dim3(1), dim3(64), 0, st, loss, 1);
     if (n > 0) {
         hipLaunchKernelGGL(k_mlp_train, dim3((unsigned)((n + TU - 1) / TU)), dim3(64), 0, st, wbf, feat, blocks, n,
-                           1.0f / (float)n, grad, loss);
+                           1.0f / (float)n, damp, grad, loss);
     }
     hipLaunchKernelGGL(k_adam, dim3((NW + 255) / 256), dim3(256), 0, st, w32, wbf, m, v, grad, t, lr);
     return hipGetLastError();

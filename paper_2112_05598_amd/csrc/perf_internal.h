@@ -116,7 +116,7 @@ hipError_t launch_features_finalize(const void* x, int x_dtype, const float* sum
 // ---------------------------------------------------------------- launchers (mlp.hip)
 hipError_t launch_mlp_infer(const uint16_t* w, const float* feat, const float* blocks, int64_t units, float* minv,
                             hipStream_t st);
-hipError_t launch_mlp_train(float* w32, uint16_t* wbf, float* m, float* v, int t, float lr, const float* feat,
+hipError_t launch_mlp_train(float* w32, uint16_t* wbf, float* m, float* v, int t, float lr, float damp, const float* feat,
                             const float* blocks, int n, float* loss, float* grad, hipStream_t st);
 
 }  // namespace perf

@@ -218,10 +218,11 @@ class Scene:
                     beta=list(st.beta[:max(k - 1, 0)]), pAp=list(st.pAp[:k + 1]), ms_phase=list(st.ms_phase[:6]), ms_jtj=st.ms_phase[6], n_jtj=int(st.ms_phase[7]))
 
 
-def mlp_train_step(w32, wbf16, m, v, t: int, lr: float, feat, blocks, loss, grad, stream=None):
-    """One Adam step of the learned preconditioner on a batch (feat [n,12], blocks [n,5])."""
+def mlp_train_step(w32, wbf16, m, v, t: int, lr: float, feat, blocks, loss, grad, stream=None, damp: float = 0.0):
+    """One Adam step of the learned preconditioner on a batch (feat [n,12], blocks [n,5]);
+    the target is the damped normalised inverse (B~ + damp I)^-1."""
     lib = abi.load()
     n = int(feat.shape[0])
     st = ctypes.c_void_p(torch.cuda.current_stream(feat.device).cuda_stream) if stream is None else stream
-    abi.check(lib.perf_mlp_train_step(_ptr(w32), _ptr(wbf16), _ptr(m), _ptr(v), int(t), ctypes.c_float(lr),
+    abi.check(lib.perf_mlp_train_step(_ptr(w32), _ptr(wbf16), _ptr(m), _ptr(v), int(t), ctypes.c_float(lr), ctypes.c_float(damp),
                                       _ptr(feat), _ptr(blocks), n, _ptr(loss), _ptr(grad), st))

@@ -87,7 +87,8 @@ def test_mlp_inference_matches_fp64_mlp(setup):
     assert np.all(np.linalg.eigvalsh(M)[:, 0] > 0)
 
 
-def test_mlp_training_gradient(setup):
+@pytest.mark.parametrize("damp", [0.0, 0.3])
+def test_mlp_training_gradient(setup, damp):
     from oracle import mlp
     from paper_2112_05598_amd.scene import mlp_train_step
     w, orc, sc, targets, t, x = setup
@@ -104,10 +105,10 @@ def test_mlp_training_gradient(setup):
     wbf = torch.from_numpy(bits.view(np.int16)).to(dev).view(torch.bfloat16).clone()
     m = torch.zeros_like(w32); v = torch.zeros_like(w32); g = torch.zeros_like(w32)
     loss = torch.zeros(1, dtype=torch.float32, device=dev)
-    mlp_train_step(w32, wbf, m, v, 1, 1e-4, fb, bb, loss, g)
+    mlp_train_step(w32, wbf, m, v, 1, 1e-4, fb, bb, loss, g, damp=damp)
     torch.cuda.synchronize()
     grad_gpu = (m / 0.1).cpu().numpy()  # first Adam step from m = 0: m = (1 - beta1) g
-    L_or, g_or = mlp.loss_and_grad(wq, fb.cpu().numpy().astype(np.float64), bb.cpu().numpy().astype(np.float64))
+    L_or, g_or = mlp.loss_and_grad(wq, fb.cpu().numpy().astype(np.float64), bb.cpu().numpy().astype(np.float64), damp)
     assert abs(loss.item() - L_or) <= 2e-2 * L_or
     cos = grad_gpu @ g_or / (np.linalg.norm(grad_gpu) * np.linalg.norm(g_or))
     assert cos >= 0.999

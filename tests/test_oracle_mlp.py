@@ -24,19 +24,64 @@ def random_blocks(n, seed):
     return b
 
 
-def test_loss_gradient_matches_finite_differences(mlp):
+def unit_errors(mlp, w, feat, blocks, damp):
+    """||L L^T (B~ + damp I) - I||_F^2 per unit, assembled independently of loss_and_grad."""
+    L = mlp.factor(mlp.forward(w, feat)[0])
+    Bn, _, live = mlp.normalised_block(blocks)
+    E = L @ np.transpose(L, (0, 2, 1)) @ (Bn + damp * np.eye(4)) - np.eye(4)
+    q = (E * E).sum(axis=(1, 2))
+    q[~live] = 0.0
+    return q
+
+
+@pytest.mark.parametrize("damp", [0.0, 0.3])
+def test_loss_gradient_matches_finite_differences(mlp, damp):
     rng = np.random.default_rng(0)
     w = mlp.init_weights(1) + 0.05 * rng.normal(size=mlp.NW)
     feat = rng.normal(size=(40, 12))
     blocks = random_blocks(40, 2)
-    loss, g = mlp.loss_and_grad(w, feat, blocks)
+    q = unit_errors(mlp, w, feat, blocks, damp)
+    # both branches of the robust loss are exercised
+    assert np.any(q > mlp.KAPPA) and np.any((q > 0) & (q < mlp.KAPPA))
+    loss, g = mlp.loss_and_grad(w, feat, blocks, damp)
+    expect = np.where(q > mlp.KAPPA, 4.0 * np.sqrt(q) - 4.0, q).sum() / 40
+    assert abs(loss - expect) <= 1e-12 * expect
     idx = rng.choice(mlp.NW, 60, replace=False)
     eps = 1e-6
     for i in idx:
         wp = w.copy(); wp[i] += eps
         wm = w.copy(); wm[i] -= eps
-        fd = (mlp.loss_and_grad(wp, feat, blocks)[0] - mlp.loss_and_grad(wm, feat, blocks)[0]) / (2 * eps)
+        fd = (mlp.loss_and_grad(wp, feat, blocks, damp)[0] - mlp.loss_and_grad(wm, feat, blocks, damp)[0]) / (2 * eps)
         assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(fd)), (i, fd, g[i])
+
+
+def test_robust_loss_is_continuous_at_kappa(mlp):
+    """Quadratic below KAPPA, 2 sqrt(KAPPA q) - KAPPA above: value and slope agree at KAPPA."""
+    k = mlp.KAPPA
+    above = lambda q: 2.0 * np.sqrt(k * q) - k  # noqa: E731
+    assert abs(above(k) - k) < 1e-12
+    h = 1e-6
+    assert abs((above(k + h) - above(k)) / h - 1.0) < 1e-5
+
+
+@pytest.mark.parametrize("damp", [0.0, 0.5])
+def test_damped_inverse_is_a_zero_of_the_loss(mlp, damp):
+    """Raw outputs from the Cholesky factor of (B~ + damp I)^-1 give zero loss and zero
+    gradient through the last layer's bias (the network reproduces them when W3 = 0)."""
+    blocks = random_blocks(30, 8)
+    Bn, dis, live = mlp.normalised_block(blocks)
+    L = np.zeros_like(Bn)
+    L[live] = np.linalg.cholesky(np.linalg.inv(Bn[live] + damp * np.eye(4)))
+    L[~live] = np.eye(4)
+    # one unit at a time: a network with W3 = 0 outputs b3 for every input
+    for u in np.nonzero(live)[0][:5]:
+        p = mlp.unpack(mlp.init_weights(3))
+        p["W3"][:] = 0.0
+        p["b3"][:] = 0.0
+        p["b3"][:10] = mlp.raw_from_factor(L[u:u + 1])[0]
+        loss, g = mlp.loss_and_grad(mlp.pack(p), np.zeros((1, 12)), blocks[u:u + 1], damp)
+        assert loss < 1e-20
+        assert np.abs(g).max() < 1e-9
 
 
 def test_exact_factor_reproduces_block_inverse(mlp, oracle_mod):
