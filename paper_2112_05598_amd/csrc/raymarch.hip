@@ -159,7 +159,11 @@ struct Tex {
 
 // Far intersection with layer l beyond tmin and its bilinear equirectangular texels.
 __device__ __forceinline__ bool env_hit(const Geo& G, const Ray& r, int l, float tmin, Tex& tx) {
-    const float R = G.radius[l];
+    // the layer's radius by selects: a computed index into the kernel-argument struct would
+    // move the whole struct to scratch memory
+    float R = G.radius[0];
+#pragma unroll
+    for (int q = 1; q < kMaxLayers; ++q) R = (l == q) ? G.radius[q] : R;
     const float b = r.o[0] * r.d[0] + r.o[1] * r.d[1] + r.o[2] * r.d[2];
     const float cc = r.o[0] * r.o[0] + r.o[1] * r.o[1] + r.o[2] * r.o[2] - R * R;
     const float disc = b * b - cc;
@@ -251,9 +255,11 @@ constexpr int kB = 8;
 constexpr int kB3 = kB * kB * kB;
 
 typedef float f4 __attribute__((ext_vector_type(4)));
+typedef float f2 __attribute__((ext_vector_type(2)));
 // explicit LDS pointers, so accesses compile to ds_* instructions rather than flat ones
 #define LDS __attribute__((address_space(3)))
 typedef LDS f4 lds_f4;
+typedef LDS f2 lds_f2;
 typedef LDS float lds_float;
 typedef LDS int lds_int;
 typedef LDS unsigned char lds_u8;
@@ -273,14 +279,14 @@ struct Window {
     __device__ __forceinline__ int coord(int a, int sa) const { return o[a] + ((sa - o[a]) & (kB - 1)); }
     // flush(x, y, z) for every window voxel, one per lane per round
     template <class Flush>
-    __device__ void each_voxel(Flush& flush) const {
+    __device__ __forceinline__ void each_voxel(Flush& flush) const {
         for (int i = lane_id(); i < kB3; i += 64) {
             const int sx = i & (kB - 1), sy = (i >> 3) & (kB - 1), sz = i >> 6;
             flush(coord(0, sx), coord(1, sy), coord(2, sz));
         }
     }
     template <class Flush>
-    __device__ void move_axis(int a, int no, Flush& flush) {
+    __device__ __forceinline__ void move_axis(int a, int no, Flush& flush) {
         const int d = no - o[a];
         if (d == 0) return;
         if (d >= kB || d <= -kB) {
@@ -358,7 +364,7 @@ struct Brick4 {
         win.fit(on, lo, hi, fl);
     }
     template <class Sink>
-    __device__ void flush_all(const Geo& G, Sink& out) {
+    __device__ __forceinline__ void flush_all(const Geo& G, Sink& out) {
         auto fl = [&](int x, int y, int z) { flush_voxel(G, x, y, z, out); };
         win.each_voxel(fl);
     }
@@ -404,10 +410,11 @@ struct Brick4 {
     }
 };
 
-// Generic accumulator with NCH scalar channels updated by LDS atomics (used by the
-// once-per-step gradient and feature passes).
+// Accumulator with NCH scalar channels updated by LDS atomics: the gradient pass flushes
+// per-ray window sums that many lanes of a wave hand over for one voxel at the same step,
+// where atomics serialise more cheaply than elections.
 template <int NCH>
-struct Brick {
+struct BrickAtomic {
     Window win;
     lds_float* s;  // [NCH][kB3]
 
@@ -435,7 +442,7 @@ struct Brick {
         if (nz && x >= 0 && y >= 0 && z >= 0 && x < G.nx && y < G.ny && z < G.nz) out((z * G.ny + y) * G.nx + x, v);
     }
     template <class F>
-    __device__ void flush_all(const Geo& G, F& out) {
+    __device__ __forceinline__ void flush_all(const Geo& G, F& out) {
         auto fl = [&](int x, int y, int z) { flush_voxel(G, x, y, z, out); };
         win.each_voxel(fl);
     }
@@ -443,6 +450,135 @@ struct Brick {
     __device__ __forceinline__ void fit(const Geo& G, bool on, const int lo[3], const int hi[3], F& out) {
         auto fl = [&](int x, int y, int z) { flush_voxel(G, x, y, z, out); };
         win.fit(on, lo, hi, fl);
+    }
+};
+
+// Accumulator with NCH = 6 or 9 channels per window voxel, updated like Brick4 by elected
+// read-modify-writes (the feature pass scatters to eight corners per sample, in rotated
+// order).  Channels 0..3 are a float4 plane; the rest a float4 plane and a float plane
+// (NCH = 9) or a float2 plane (NCH = 6).
+template <int NCH>
+struct Brick {
+    static_assert(NCH == 6 || NCH == 9, "6 or 9 channels");
+    Window win;
+    volatile lds_f4* s4;    // [kB3] channels 0..3
+    volatile lds_f4* s4b;   // [kB3] channels 4..7 (NCH = 9)
+    volatile lds_float* s1; // [kB3] channel 8 (NCH = 9)
+    volatile lds_f2* s2;    // [kB3] channels 4..5 (NCH = 6)
+    volatile lds_u8* tag;   // [kB3] lane ids
+
+    __device__ __forceinline__ void init(f4* base, unsigned char* tb) {
+        s4 = (volatile lds_f4*)base;
+        if constexpr (NCH == 9) {
+            s4b = (volatile lds_f4*)(base + kB3);
+            s1 = (volatile lds_float*)(base + 2 * kB3);
+        } else {
+            s2 = (volatile lds_f2*)(base + kB3);
+        }
+        tag = (volatile lds_u8*)tb;
+        win.o[0] = win.o[1] = win.o[2] = -(1 << 24);
+        float* f = (float*)base;
+        for (int i = lane_id(); i < NCH * kB3; i += 64) ((volatile lds_float*)f)[i] = 0.0f;
+    }
+    __device__ __forceinline__ bool inside(const int lo[3], const int hi[3]) const { return win.inside(lo, hi); }
+    __device__ __forceinline__ void rmw(int sl, const float v[NCH]) {
+        s4[sl] = s4[sl] + f4{v[0], v[1], v[2], v[3]};
+        if constexpr (NCH == 9) {
+            s4b[sl] = s4b[sl] + f4{v[4], v[5], v[6], v[7]};
+            s1[sl] = s1[sl] + v[8];
+        } else {
+            s2[sl] = s2[sl] + f2{v[4], v[5]};
+        }
+    }
+    // add v to voxel (x, y, z) for every active lane that calls (each lane one voxel)
+    __device__ __forceinline__ void add(int x, int y, int z, const float v[NCH]) {
+        const int sl = ring_slot(x, y, z);
+        const unsigned char lane = (unsigned char)lane_id();
+        bool pend = true;
+        while (wave_any(pend)) {
+            if (pend) tag[sl] = lane;
+            if (pend && tag[sl] == lane) {
+                rmw(sl, v);
+                pend = false;
+            }
+        }
+    }
+    template <class F>
+    __device__ __forceinline__ void flush_voxel(const Geo& G, int x, int y, int z, F& out) {
+        const int sl = ring_slot(x, y, z);
+        float v[NCH];
+        const f4 a = s4[sl];
+        s4[sl] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+        v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+        if constexpr (NCH == 9) {
+            const f4 b = s4b[sl];
+            s4b[sl] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+            v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+            v[8] = s1[sl];
+            s1[sl] = 0.0f;
+        } else {
+            const f2 b = s2[sl];
+            s2[sl] = f2{0.0f, 0.0f};
+            v[4] = b.x; v[5] = b.y;
+        }
+        bool nz = false;
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) nz |= v[c] != 0.0f;
+        if (nz && x >= 0 && y >= 0 && z >= 0 && x < G.nx && y < G.ny && z < G.nz) out((z * G.ny + y) * G.nx + x, v);
+    }
+    template <class F>
+    __device__ __forceinline__ void flush_all(const Geo& G, F& out) {
+        auto fl = [&](int x, int y, int z) { flush_voxel(G, x, y, z, out); };
+        win.each_voxel(fl);
+    }
+    template <class F>
+    __device__ __forceinline__ void fit(const Geo& G, bool on, const int lo[3], const int hi[3], F& out) {
+        auto fl = [&](int x, int y, int z) { flush_voxel(G, x, y, z, out); };
+        win.fit(on, lo, hi, fl);
+    }
+    // add w_i * base to the 8 corners of every lane that is on (uniform call; NCH = 6), the
+    // corners visited in an order rotated by pixel position as in Brick4
+    template <class Sink>
+    __device__ __forceinline__ void scatter8(const Geo& G, bool on, bool inb, const Corners& c, const float base[NCH],
+                                             Sink& out) {
+        if (wave_any(on && !inb)) {
+            if (on && !inb) {
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const int x = c.i[0] + (i & 1), y = c.i[1] + ((i >> 1) & 1), z = c.i[2] + (i >> 2);
+                    float vv[NCH];
+#pragma unroll
+                    for (int q = 0; q < NCH; ++q) vv[q] = base[q] * c.w[i];
+                    out((z * G.ny + y) * G.nx + x, vv);
+                }
+            }
+        }
+        const bool mine = on && inb;
+        if (!wave_any(mine)) return;
+        const unsigned char lane = (unsigned char)lane_id();
+        const int phi = ((lane & 7) + 3 * (lane >> 3)) & 7;
+        const int sx0 = c.i[0] & 7, sx1 = (c.i[0] + 1) & 7;
+        const int sy0 = (c.i[1] & 7) << 3, sy1 = ((c.i[1] + 1) & 7) << 3;
+        const int sz0 = (c.i[2] & 7) << 6, sz1 = ((c.i[2] + 1) & 7) << 6;
+        const float wx0 = 1.0f - c.f[0], wy0 = 1.0f - c.f[1], wz0 = 1.0f - c.f[2];
+#pragma unroll 1
+        for (int r = 0; r < 8; ++r) {
+            const int i = (r + phi) & 7;
+            const bool bx = i & 1, by = i & 2, bz = i & 4;
+            const int sl = (bz ? sz1 : sz0) + (by ? sy1 : sy0) + (bx ? sx1 : sx0);
+            const float w = (bx ? c.f[0] : wx0) * (by ? c.f[1] : wy0) * (bz ? c.f[2] : wz0);
+            float v[NCH];
+#pragma unroll
+            for (int q = 0; q < NCH; ++q) v[q] = base[q] * w;
+            bool pend = mine;
+            while (wave_any(pend)) {
+                if (pend) tag[sl] = lane;
+                if (pend && tag[sl] == lane) {
+                    rmw(sl, v);
+                    pend = false;
+                }
+            }
+        }
     }
 };
 
@@ -786,72 +922,83 @@ __device__ __forceinline__ void adjoint_scatter(const Geo& G, const Ray& r, bool
 // Per-ray window over the current 8 corners.  A voxel is a corner of a contiguous run of
 // a ray's samples (its corner region is a box and the ray is a line), so a voxel that
 // leaves the window never returns: flushing on leave aggregates the ray's partials per
-// voxel exactly before they are squared into the block.  The flushed per-ray products
-// (gradient and block entries, linear in the rays) are then combined per wave in LDS.
-struct Win {
-    int i[3];
-    float a[8], s0[8], s1[8], s2[8];
+// voxel exactly before they are squared into the block.  Register slot b holds the window
+// voxel whose coordinate parities are the bits of b, so a voxel entering the window takes
+// the slot of the one that left and nothing moves.  The flushed per-ray products
+// (gradient and block entries, linear in the rays) are combined per wave in LDS.
+struct GradWin {
+    int i[3];                          // low corner of the window
+    float a[8], s0[8], s1[8], s2[8];   // per slot: sum w A and sum w d_sigma (3 colours)
 };
 
-struct GradOut {
-    const Geo& G;
-    Brick<9>& B;
-    SinkGrad sink;
-    float rr[3];
-    __device__ __forceinline__ void unit(int x, int y, int z, float a, float s0, float s1, float s2) {
-        if (a == 0.0f && s0 == 0.0f && s1 == 0.0f && s2 == 0.0f) return;
-        const float v[9] = {-a * rr[0],    -a * rr[1], -a * rr[2], -(s0 * rr[0] + s1 * rr[1] + s2 * rr[2]),
-                            a * a,         a * s0,     a * s1,     a * s2,
-                            s0 * s0 + s1 * s1 + s2 * s2};
-        const int lo[3] = {x, y, z};
-        if (B.inside(lo, lo)) B.add(x, y, z, v);
-        else sink((z * G.ny + y) * G.nx + x, v);
+// slots whose voxel leaves when the window's low corner moves from w to c (at most one cell
+// per axis per sample; a larger jump empties the whole window)
+__device__ __forceinline__ unsigned leaving_slots(const int w[3], const int c[3]) {
+    constexpr unsigned kBit0[3] = {0x55u, 0x33u, 0x0Fu};  // slots with bit a = 0
+    unsigned m = 0u;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const int d = c[a] - w[a];
+        if (d != 0) {
+            const int gone = d > 0 ? w[a] : w[a] + 1;  // coordinate left behind
+            m |= (d > 1 || d < -1) ? 0xFFu : ((gone & 1) ? (~kBit0[a] & 0xFFu) : kBit0[a]);
+        }
     }
-};
-
-__device__ __forceinline__ void win_flush_slot(Win& w, int b, GradOut& out) {
-    out.unit(w.i[0] + (b & 1), w.i[1] + ((b >> 1) & 1), w.i[2] + ((b >> 2) & 1), w.a[b], w.s0[b], w.s1[b], w.s2[b]);
+    return m;
 }
 
-template <int AX>
-__device__ __forceinline__ void win_shift(Win& w, int target, GradOut& out) {
-    constexpr int bit = 1 << AX;
-    const int delta = target - w.i[AX];
-    if (delta == 0) return;
-    if (delta == 1) {
+template <int SLOT>
+__device__ __forceinline__ void grad_flush_slot(const Geo& G, unsigned pend, const GradWin& w, const float rr[3],
+                                                BrickAtomic<9>& B, const SinkGrad& sink) {
+    const bool mine = (pend >> SLOT) & 1u;
+    if (!wave_any(mine)) return;
+    if (!mine) return;
+    const int x = w.i[0] + (((SLOT >> 0) ^ w.i[0]) & 1);
+    const int y = w.i[1] + (((SLOT >> 1) ^ w.i[1]) & 1);
+    const int z = w.i[2] + (((SLOT >> 2) ^ w.i[2]) & 1);
+    const float a = w.a[SLOT], s0 = w.s0[SLOT], s1 = w.s1[SLOT], s2 = w.s2[SLOT];
+    const float v[9] = {-a * rr[0], -a * rr[1], -a * rr[2], -(s0 * rr[0] + s1 * rr[1] + s2 * rr[2]),
+                        a * a,      a * s0,     a * s1,     a * s2,
+                        s0 * s0 + s1 * s1 + s2 * s2};
+    const int lo[3] = {x, y, z};
+    if (B.inside(lo, lo)) B.add(x, y, z, v);
+    else sink((z * G.ny + y) * G.nx + x, v);
+}
+
+__device__ __forceinline__ void grad_flush(const Geo& G, unsigned pend, GradWin& w, const float rr[3], BrickAtomic<9>& B,
+                                           const SinkGrad& sink) {
+    grad_flush_slot<0>(G, pend, w, rr, B, sink);
+    grad_flush_slot<1>(G, pend, w, rr, B, sink);
+    grad_flush_slot<2>(G, pend, w, rr, B, sink);
+    grad_flush_slot<3>(G, pend, w, rr, B, sink);
+    grad_flush_slot<4>(G, pend, w, rr, B, sink);
+    grad_flush_slot<5>(G, pend, w, rr, B, sink);
+    grad_flush_slot<6>(G, pend, w, rr, B, sink);
+    grad_flush_slot<7>(G, pend, w, rr, B, sink);
+}
+
+__device__ __forceinline__ unsigned nonzero_slots(const GradWin& w) {
+    unsigned m = 0u;
 #pragma unroll
-        for (int b = 0; b < 8; ++b) {
-            if (!(b & bit)) {
-                win_flush_slot(w, b, out);
-                w.a[b] = w.a[b | bit]; w.s0[b] = w.s0[b | bit]; w.s1[b] = w.s1[b | bit]; w.s2[b] = w.s2[b | bit];
-                w.a[b | bit] = 0.0f; w.s0[b | bit] = 0.0f; w.s1[b | bit] = 0.0f; w.s2[b | bit] = 0.0f;
-            }
-        }
-    } else if (delta == -1) {
+    for (int b = 0; b < 8; ++b)
+        if (w.a[b] != 0.0f || w.s0[b] != 0.0f || w.s1[b] != 0.0f || w.s2[b] != 0.0f) m |= 1u << b;
+    return m;
+}
+
+__device__ __forceinline__ void clear_slots(GradWin& w, unsigned m) {
 #pragma unroll
-        for (int b = 0; b < 8; ++b) {
-            if (b & bit) {
-                win_flush_slot(w, b, out);
-                w.a[b] = w.a[b ^ bit]; w.s0[b] = w.s0[b ^ bit]; w.s1[b] = w.s1[b ^ bit]; w.s2[b] = w.s2[b ^ bit];
-                w.a[b ^ bit] = 0.0f; w.s0[b ^ bit] = 0.0f; w.s1[b ^ bit] = 0.0f; w.s2[b ^ bit] = 0.0f;
-            }
-        }
-    } else {
-#pragma unroll
-        for (int b = 0; b < 8; ++b) {
-            win_flush_slot(w, b, out);
+    for (int b = 0; b < 8; ++b) {
+        if (m & (1u << b)) {
             w.a[b] = 0.0f; w.s0[b] = 0.0f; w.s1[b] = 0.0f; w.s2[b] = 0.0f;
         }
     }
-    w.i[AX] = target;
 }
 
 template <int PD>
 __device__ __forceinline__ void grad_scatter(const Geo& G, const Ray& r, bool live, XL<PD> X, const float rr[3],
-                                             Depth depth, Brick<9>& B, TexTable<9>& TT, float* __restrict__ grad,
+                                             Depth depth, BrickAtomic<9>& B, TexTable<9>& TT, float* __restrict__ grad,
                                              float* __restrict__ blocks) {
     SinkGrad sink{grad, blocks};
-    GradOut out{G, B, sink, {rr[0], rr[1], rr[2]}};
     const float Tx = exp_neg(depth.value());
     float S[3] = {0.0f, 0.0f, 0.0f};
     if (live) {
@@ -873,13 +1020,11 @@ __device__ __forceinline__ void grad_scatter(const Geo& G, const Ray& r, bool li
         env_back<PD>(G, r, X, Tx, S, emit);
     }
     TT.flush(sink);
-    Win w;
-#pragma unroll
-    for (int b = 0; b < 8; ++b) {
-        w.a[b] = 0.0f; w.s0[b] = 0.0f; w.s1[b] = 0.0f; w.s2[b] = 0.0f;
-    }
+    GradWin w;
     w.i[0] = w.i[1] = w.i[2] = 0;
-    bool started = false;
+    clear_slots(w, 0xFFu);
+    bool started = false;  // the window holds this ray's sums
+    bool ended = false;    // the ray's last sample is in the window, to be flushed whole
     // G_k from the back, starting with the environment seen from the grid exit
     float G0 = Tx * S[0], G1 = Tx * S[1], G2 = Tx * S[2];
     float Tn = Tx;
@@ -894,29 +1039,34 @@ __device__ __forceinline__ void grad_scatter(const Geo& G, const Ray& r, bool li
         const int k = r.K - 1 - m;
         Corners c;
         float dk = 0.0f;
-        int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+        int lo[3] = {w.i[0], w.i[1], w.i[2]}, hi[3] = {w.i[0] + 1, w.i[1] + 1, w.i[2] + 1};
         if (on) {
             float g[3];
             dk = sample_at(G, r, k, g);
             corners(G, g, c);
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
-                // cover the corners about to leave the lane's window as well as the new ones
+                // cover the voxels about to leave the lane's window as well as the new ones
                 const int prev = started ? w.i[a] : c.i[a];
                 lo[a] = min(prev, c.i[a]);
                 hi[a] = max(prev, c.i[a]) + 1;
             }
         }
-        B.fit(G, on, lo, hi, sink);
-        if (!on) continue;
-        if (!started) {
-            w.i[0] = c.i[0]; w.i[1] = c.i[1]; w.i[2] = c.i[2];
-            started = true;
-        } else {
-            win_shift<0>(w, c.i[0], out);
-            win_shift<1>(w, c.i[1], out);
-            win_shift<2>(w, c.i[2], out);
+        B.fit(G, on || ended, lo, hi, sink);
+        unsigned pend = 0u;
+        if (ended) pend = 0xFFu;
+        else if (on && started) pend = leaving_slots(w.i, c.i);
+        if (pend) pend &= nonzero_slots(w);
+        grad_flush(G, pend, w, rr, B, sink);
+        if (ended) {
+            clear_slots(w, 0xFFu);
+            ended = false;
+            started = false;
         }
+        if (!on) continue;
+        if (started) clear_slots(w, leaving_slots(w.i, c.i));
+        w.i[0] = c.i[0]; w.i[1] = c.i[1]; w.i[2] = c.i[2];
+        started = true;
         float sg, c0, c1, c2;
         gather<PD>(X, c, nx, nxy, sg, c0, c1, c2);
         const float tau = sg * dk;
@@ -931,17 +1081,31 @@ __device__ __forceinline__ void grad_scatter(const Geo& G, const Ray& r, bool li
         G1 += A * c1;
         G2 += A * c2;
         Tn = T;
+        // slot b holds the corner whose offset along axis a is bit a of b xor the parity of
+        // c.i[a]: its weight is the product of the per-axis weights
+        float gw[3][2];
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            w.a[i] += c.w[i] * A;
-            w.s0[i] += c.w[i] * ds0;
-            w.s1[i] += c.w[i] * ds1;
-            w.s2[i] += c.w[i] * ds2;
+        for (int a = 0; a < 3; ++a) {
+            const bool odd = c.i[a] & 1;
+            gw[a][0] = odd ? c.f[a] : 1.0f - c.f[a];
+            gw[a][1] = odd ? 1.0f - c.f[a] : c.f[a];
         }
-        if (k == 0) {
 #pragma unroll
-            for (int b = 0; b < 8; ++b) win_flush_slot(w, b, out);
+        for (int b = 0; b < 8; ++b) {
+            const float wb = gw[0][b & 1] * gw[1][(b >> 1) & 1] * gw[2][b >> 2];
+            w.a[b] += wb * A;
+            w.s0[b] += wb * ds0;
+            w.s1[b] += wb * ds1;
+            w.s2[b] += wb * ds2;
         }
+        if (k == 0) ended = true;
+    }
+    // rays whose last sample came in the final step
+    {
+        const int lo[3] = {w.i[0], w.i[1], w.i[2]}, hi[3] = {w.i[0] + 1, w.i[1] + 1, w.i[2] + 1};
+        B.fit(G, ended, lo, hi, sink);
+        unsigned pend = ended ? nonzero_slots(w) : 0u;
+        grad_flush(G, pend, w, rr, B, sink);
     }
     B.flush_all(G, sink);
 }
@@ -1000,15 +1164,8 @@ __device__ __forceinline__ void feature_scatter(const Geo& G, const Ray& r, bool
         const float T = (k == 0) ? 1.0f : exp_neg(depth.value());
         const float al = one_minus_exp_neg(tau, exp_neg(tau));
         const float A = T * al;
-        const bool inb = B.inside(lo, hi);
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const float w = c.w[i];
-            const float v[6] = {w, w * T, w * G0, w * G1, w * G2, w * al};
-            const int x = c.i[0] + (i & 1), yy = c.i[1] + ((i >> 1) & 1), z = c.i[2] + (i >> 2);
-            if (inb) B.add(x, yy, z, v);
-            else sink((z * G.ny + yy) * G.nx + x, v);
-        }
+        const float base6[6] = {1.0f, T, G0, G1, G2, al};
+        B.scatter8(G, true, B.inside(lo, hi), c, base6, sink);
         G0 += A * c0;
         G1 += A * c1;
         G2 += A * c2;
@@ -1069,9 +1226,9 @@ __global__ __launch_bounds__(kBlock) void k_ray(Geo G, RayArgs A) {
     constexpr int NCH = Lds<MODE>::NCH;
     constexpr bool SCATTER = Lds<MODE>::SCATTER;
     constexpr bool JT = MODE == M_VJP || MODE == M_JTJ;
-    __shared__ float s_brick[(SCATTER && !JT) ? kWaves * NCH * kB3 : 1];
+    __shared__ f4 s_brick[(SCATTER && !JT) ? kWaves * NCH * kB3 / 4 : 1];
     __shared__ f4 s_brick4[JT ? kWaves * kB3 : 1];
-    __shared__ unsigned char s_tag[JT ? kWaves * kB3 : 1];
+    __shared__ unsigned char s_tag[SCATTER ? kWaves * kB3 : 1];
     __shared__ float s_tab[SCATTER ? kWaves * NCH * 64 : 1];
     __shared__ int s_keys[SCATTER ? kWaves * 64 : 1];
     if (A.done && *A.done) return;
@@ -1136,8 +1293,8 @@ __global__ __launch_bounds__(kBlock) void k_ray(Geo G, RayArgs A) {
             }
             adjoint_scatter<PD>(G, r, p.active, X, u, depth, B, TT, A.y);
         } else if constexpr (MODE == M_GRAD) {
-            Brick<NCH> B;
-            B.init(s_brick + wave * NCH * kB3);
+            BrickAtomic<NCH> B;
+            B.init((float*)(s_brick + wave * NCH * kB3 / 4));
             float res[3] = {0.0f, 0.0f, 0.0f};
             if (p.active && A.targets) {
 #pragma unroll
@@ -1149,7 +1306,7 @@ __global__ __launch_bounds__(kBlock) void k_ray(Geo G, RayArgs A) {
             grad_scatter<PD>(G, r, p.active, X, res, depth, B, TT, A.y, A.blocks);
         } else {
             Brick<NCH> B;
-            B.init(s_brick + wave * NCH * kB3);
+            B.init(s_brick + wave * NCH * kB3 / 4, s_tag + wave * kB3);
             feature_scatter<PD>(G, r, p.active, X, depth, B, TT, A.y);
         }
     }
