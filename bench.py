@@ -49,27 +49,30 @@ def measured_traffic(n_jtj_units: float):
     return rec.get("bytes_per_dispatch")
 
 
-def cpu_baseline(w, max_seconds: float = 20.0):
-    """The FP64 oracle's J^T J v on a strided sample of the same rays, on the host cores."""
+def cpu_baseline(w, min_seconds: float = 10.0):
+    """The FP64 oracle's J^T J v on a strided sample of the same rays, on the host cores.
+
+    A call has a fixed cost (per-thread FP64 accumulators of P doubles, summed at the end), so
+    the sample grows until one call takes at least min_seconds (or covers every ray)."""
     import numpy as np
     import oracle
     orc = oracle.OracleScene(w.spec, w.cams)
     v = np.random.default_rng(7).normal(size=orc.n_params)
     x = w.x_init.astype(np.float64)
-    # calibrate on a small sample, then size the timed sample to ~max_seconds
-    probe = np.arange(0, orc.n_rays, max(orc.n_rays // 4096, 1), dtype=np.int64)
-    t0 = time.perf_counter()
-    orc.apply_JtJ(x, v, rays=probe)
-    per_ray = (time.perf_counter() - t0) / len(probe)
-    n = int(min(orc.n_rays, max(4096, max_seconds / max(per_ray, 1e-9))))
-    stride = max(orc.n_rays // n, 1)
-    sample = np.arange(0, orc.n_rays, stride, dtype=np.int64)
-    t0 = time.perf_counter()
-    orc.apply_JtJ(x, v, rays=sample)
-    dt = time.perf_counter() - t0
+    n = 16384
+    while True:
+        stride = max(orc.n_rays // n, 1)
+        sample = np.arange(0, orc.n_rays, stride, dtype=np.int64)
+        t0 = time.perf_counter()
+        orc.apply_JtJ(x, v, rays=sample)
+        dt = time.perf_counter() - t0
+        print(f"[bench] oracle: {len(sample)} rays in {dt:.1f} s", file=sys.stderr, flush=True)
+        if dt >= min_seconds or stride == 1:
+            break
+        n = int(len(sample) * min(8.0, 1.5 * min_seconds / max(dt, 1e-3)))
     return {"value": len(sample) / dt, "unit": "rays/s", "cores": orc.num_threads(), "kind": "oracle",
-            "sample": f"J^T J v over every {stride}-th ray ({len(sample)} of {orc.n_rays} rays), FP64, "
-                      f"{dt:.1f} s"}
+            "sample": f"J^T J v over every {stride}-th ray ({len(sample)} of {orc.n_rays} rays) at the initial "
+                      f"parameters, FP64, {dt:.1f} s"}
 
 
 def main():
@@ -82,6 +85,8 @@ def main():
     ap.add_argument("--precond", default="jacobi")
     ap.add_argument("--dtype", default="f32", choices=["f32", "bf16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the learned-preconditioner GN run to the Jacobi run's final objective")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (the ray-sharded design is "
@@ -98,13 +103,13 @@ def main():
     w = ps.workload(args.workload)
     print(f"[bench] workload {w.name}: grid {w.spec.nx}^3, {w.spec.n_layers} layers {w.spec.env_w}x{w.spec.env_h}, "
           f"{w.cams.n} cams {w.cams.width}x{w.cams.height}, P={w.spec.n_params}", file=sys.stderr, flush=True)
-    sc = Scene(w.spec, w.cams, None, param_dtype="f32", device="cuda:0")
+    sc = Scene(w.spec, w.cams, None, param_dtype="f32", learned=not args.no_learned, device="cuda:0")
     x_gt = torch.from_numpy(w.x_gt).to(dev)
     H, _ = sc.render_residuals(x_gt)           # no targets yet: the render itself
     targets = H.clone()
     sc.set_targets(targets)
     if args.dtype == "bf16":
-        sc = Scene(w.spec, w.cams, targets, param_dtype="bf16", device="cuda:0")
+        sc = Scene(w.spec, w.cams, targets, param_dtype="bf16", learned=not args.no_learned, device="cuda:0")
     _, tot = sc.footprint(per_ray=False)
     tot = tot.cpu().numpy()
     bytes_per_launch = 48.0 * float(tot[0]) + 192.0 * float(tot[1])
@@ -161,6 +166,23 @@ def main():
                "pcg_iters": [s["pcg_iters"] for s in stats], "gamma": [s["gamma"] for s in stats]},
         "footprint": {"sum_U": int(tot[0]), "layer_hits": int(tot[1]), "rays_in_grid": int(tot[2])},
     }
+    if not args.no_learned and args.precond == "jacobi":
+        # GN time-to-residual: the learned preconditioner, from the same start, until it reaches
+        # the objective the timed Jacobi steps ended at (same PCG iterations per step)
+        from paper_2112_05598_amd import learned as lrn
+        sc.mlp_set_weights(lrn.load_weights(device="cuda:0"))
+        F_target = stats[-1]["F_after"]
+        run = lrn.gn_run(sc, x0, "learned", args.steps + 3, args.pcg, F_stop=F_target)
+        print(f"[bench] learned: {run['gn_steps']} GN steps, {run['pcg_iters']} PCG iterations, "
+              f"{run['ms']:.0f} ms to F {run['F'][-1]:.6g} (Jacobi: {args.steps} steps, "
+              f"{sum(s['pcg_iters'] for s in stats)} iterations, {dt * 1e3:.0f} ms to F {F_target:.6g})",
+              file=sys.stderr, flush=True)
+        out["gn_learned_vs_jacobi"] = {
+            "target_F": F_target,
+            "jacobi": {"gn_steps": args.steps, "pcg_iters": sum(s["pcg_iters"] for s in stats), "ms": dt * 1e3},
+            "learned": {"gn_steps": run["gn_steps"], "pcg_iters": run["pcg_iters"], "ms": run["ms"],
+                        "F": run["F"], "reached": run["F"][-1] <= F_target},
+            "weights": "paper_2112_05598_amd/weights/precond_mlp_bf16.npy"}
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a ray sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w)
