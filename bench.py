@@ -37,14 +37,14 @@ def kernel_sha() -> str:
     return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
 
 
-def measured_traffic(n_jtj_units: float):
+def measured_traffic(workload: str):
     """HBM bytes per J^T J v launch from committed rocprofv3 counters, if they were taken on
-    the current kernel source; None otherwise."""
+    the current kernel source and this workload; None otherwise."""
     try:
         rec = json.load(open(TRAFFIC_FILE))
     except (OSError, ValueError):
         return None
-    if rec.get("kernel_sha") != kernel_sha():
+    if rec.get("kernel_sha") != kernel_sha() or rec.get("workload") != workload:
         return None
     return rec.get("bytes_per_dispatch")
 
@@ -137,7 +137,7 @@ def main():
     jtj_ms = sum(s["ms_jtj"] for s in stats) / max(n_jtj, 1)
     value = sc.n_rays * n_jtj / dt
     achieved = bytes_per_launch / (jtj_ms * 1e-3) / 1e9
-    traffic = measured_traffic(n_jtj)
+    traffic = measured_traffic(args.workload)
     out = {
         "metric": "J^T J.v rays/s (% HBM roofline); GN time-to-residual, learned vs Jacobi PCG",
         "value": value,
