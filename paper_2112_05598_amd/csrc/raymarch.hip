@@ -212,6 +212,14 @@ __device__ __forceinline__ float one_minus_exp_neg(float t, float e) {
     return fabsf(t) < 0.25f ? series : 1.0f - e;
 }
 
+// ------------------------------------------------------------------ lane swaps (DPP)
+// Value of lane ^ 1 (quad permutation 1,0,3,2) and of lane ^ 8 (rotation by 8 inside each
+// row of 16 lanes).  Called with every lane of the wave active.
+__device__ __forceinline__ int dpp_xor1(int v) { return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false); }
+__device__ __forceinline__ int dpp_row_xor8(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x128, 0xF, 0xF, false); }
+__device__ __forceinline__ float dpp_xor1(float v) { return __int_as_float(dpp_xor1(__float_as_int(v))); }
+__device__ __forceinline__ float dpp_row_xor8(float v) { return __int_as_float(dpp_row_xor8(__float_as_int(v))); }
+
 // ------------------------------------------------------------------ wave helpers
 __device__ __forceinline__ int wave_min_i(int v) {
 #pragma unroll
@@ -256,6 +264,10 @@ constexpr int kB3 = kB * kB * kB;
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef float f2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ f4 dpp_xor1(f4 v) { return f4{dpp_xor1(v.x), dpp_xor1(v.y), dpp_xor1(v.z), dpp_xor1(v.w)}; }
+__device__ __forceinline__ f4 dpp_row_xor8(f4 v) {
+    return f4{dpp_row_xor8(v.x), dpp_row_xor8(v.y), dpp_row_xor8(v.z), dpp_row_xor8(v.w)};
+}
 // explicit LDS pointers, so accesses compile to ds_* instructions rather than flat ones
 #define LDS __attribute__((address_space(3)))
 typedef LDS f4 lds_f4;
@@ -368,7 +380,13 @@ struct Brick4 {
         auto fl = [&](int x, int y, int z) { flush_voxel(G, x, y, z, out); };
         win.each_voxel(fl);
     }
-    // add val * weight(corner) to the 8 corners of every lane that is on (uniform call)
+    // add val * weight(corner) to the 8 corners of every lane that is on (uniform call).
+    // Lanes of one grid cell share all eight corners.  Before the election, each lane adds in
+    // the contribution of its x neighbour (lane ^ 1) and then of its y neighbour (lane ^ 8)
+    // when they sit in the same cell, through DPP lane swaps, so one lane per combined group
+    // enters the election.  Lanes of different cells never target one voxel with the same
+    // corner index, so every lane of a 2x2 lane quad visits the corners in the same order,
+    // rotated per quad to spread same-cell lanes of different quads over the corners.
     template <class Sink>
     __device__ __forceinline__ void scatter8(const Geo& G, bool on, bool inb, const Corners& c, f4 val, Sink& out) {
         if (wave_any(on && !inb)) {  // corners outside the window: straight to HBM
@@ -384,9 +402,20 @@ struct Brick4 {
         }
         const bool mine = on && inb;
         if (!wave_any(mine)) return;
-        const unsigned char lane = (unsigned char)lane_id();
-        const int phi = ((lane & 7) + 3 * (lane >> 3)) & 7;
-        // ring-slot parts and axis weights of the two corners along each axis
+        const int lane = lane_id();
+        const unsigned char tag_id = (unsigned char)lane;
+        // which neighbours fold into this lane, and whether this lane keeps a contribution.
+        // The swaps run in straight-line code with every lane active: a lane swap executed
+        // under a partial mask would read the other lane's register as it was last written.
+        const int key = mine ? c.v : -1;
+        const int kx = dpp_xor1(key);
+        const bool gx = mine & (kx == key);                        // x neighbour in the same cell
+        const bool keep_x = mine & !(gx & ((lane & 1) != 0));      // the odd lane of a pair gives
+        const int key2 = keep_x ? key : -1;
+        const int ky = dpp_row_xor8(key2);
+        const bool gy = keep_x & (ky == key2);                     // y neighbour (after x) too
+        const bool keep = keep_x & !(gy & (((lane >> 3) & 1) != 0));
+        const int phi = (((lane & 7) >> 1) + 3 * (lane >> 4)) & 7;
         const int sx0 = c.i[0] & 7, sx1 = (c.i[0] + 1) & 7;
         const int sy0 = (c.i[1] & 7) << 3, sy1 = ((c.i[1] + 1) & 7) << 3;
         const int sz0 = (c.i[2] & 7) << 6, sz1 = ((c.i[2] + 1) & 7) << 6;
@@ -396,12 +425,16 @@ struct Brick4 {
             const int i = (r + phi) & 7;
             const bool bx = i & 1, by = i & 2, bz = i & 4;
             const int sl = (bz ? sz1 : sz0) + (by ? sy1 : sy0) + (bx ? sx1 : sx0);
-            const float w = (bx ? c.f[0] : wx0) * (by ? c.f[1] : wy0) * (bz ? c.f[2] : wz0);
-            const f4 add = val * w;
-            bool pend = mine;
+            const float w = mine ? (bx ? c.f[0] : wx0) * (by ? c.f[1] : wy0) * (bz ? c.f[2] : wz0) : 0.0f;
+            f4 add = val * w;
+            const f4 ax = dpp_xor1(add);
+            if (gx) add += ax;
+            const f4 ay = dpp_row_xor8(add);
+            if (gy) add += ay;
+            bool pend = keep;
             while (wave_any(pend)) {
-                if (pend) tag[sl] = lane;
-                if (pend && tag[sl] == lane) {
+                if (pend) tag[sl] = tag_id;
+                if (pend && tag[sl] == tag_id) {
                     s[sl] = s[sl] + add;
                     pend = false;
                 }
