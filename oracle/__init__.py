@@ -23,5 +23,6 @@ from .core import (  # noqa: F401
     line_search,
     project,
     gn_step,
+    upsample,
     PCGResult,
 )

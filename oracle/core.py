@@ -418,6 +418,62 @@ def project(spec, x: np.ndarray) -> np.ndarray:
     return y.reshape(-1)
 
 
+# ------------------------------------------------------------------ hierarchy (Sec. IV, hierarchical formulation)
+
+def _shortest_side(spec) -> float:
+    return min((spec.bbox_max[a] - spec.bbox_min[a]) / n for a, n in enumerate((spec.nx, spec.ny, spec.nz)))
+
+
+def _lerp_axis(n_src: int, n_dst: int, periodic: bool):
+    """For every destination cell centre along one axis: the two source indices and the weight
+    of the upper one, cell-centred coordinates (source coordinate g = (j + 0.5) n_src / n_dst
+    - 0.5); clamped to [0, n_src - 1] (lower index at most n_src - 2), or wrapped if periodic."""
+    j = np.arange(n_dst, dtype=np.float64)
+    g = (j + 0.5) * n_src / n_dst - 0.5
+    if periodic:
+        i0 = np.floor(g)
+        f = g - i0
+        i0 = i0.astype(np.int64) % n_src
+        i1 = (i0 + 1) % n_src
+    else:
+        g = np.clip(g, 0.0, n_src - 1.0)
+        i0 = np.minimum(np.floor(g).astype(np.int64), n_src - 2)
+        f = g - i0
+        i1 = i0 + 1
+    return i0, i1, f
+
+
+def upsample(spec_from, x_from: np.ndarray, spec_to) -> np.ndarray:
+    """Parameters of the next hierarchical level from the current one by linear interpolation
+    (Sec. IV): trilinear over the voxel grid, bilinear over each environment layer (periodic
+    in azimuth, clamped in polar angle), at the new cell / texel centres.  sigma is an optical
+    depth per shortest voxel side (the reading of delta), so it is scaled by the ratio of the
+    new side to the old one; colours and texel opacities are interpolated as they are.
+    Requires the same bounding box and environment layers."""
+    xf = np.asarray(x_from, dtype=np.float64)
+    nv = spec_from.n_vox
+    grid = xf[:4 * nv].reshape(spec_from.nz, spec_from.ny, spec_from.nx, 4)
+    env = xf[4 * nv:].reshape(spec_from.n_layers, spec_from.env_h, spec_from.env_w, 4)
+    ix0, ix1, fx = _lerp_axis(spec_from.nx, spec_to.nx, False)
+    iy0, iy1, fy = _lerp_axis(spec_from.ny, spec_to.ny, False)
+    iz0, iz1, fz = _lerp_axis(spec_from.nz, spec_to.nz, False)
+    out = np.zeros((spec_to.nz, spec_to.ny, spec_to.nx, 4))
+    for bz, (iz, wz) in enumerate(((iz0, 1.0 - fz), (iz1, fz))):
+        for by, (iy, wy) in enumerate(((iy0, 1.0 - fy), (iy1, fy))):
+            for bx, (ix, wx) in enumerate(((ix0, 1.0 - fx), (ix1, fx))):
+                w = wz[:, None, None] * wy[None, :, None] * wx[None, None, :]
+                out += w[..., None] * grid[np.ix_(iz, iy, ix)]
+    out[..., 3] *= _shortest_side(spec_to) / _shortest_side(spec_from)
+    iu0, iu1, fu = _lerp_axis(spec_from.env_w, spec_to.env_w, True)
+    iv0, iv1, fv = _lerp_axis(spec_from.env_h, spec_to.env_h, False)
+    eout = np.zeros((spec_to.n_layers, spec_to.env_h, spec_to.env_w, 4))
+    for (iv, wv) in ((iv0, 1.0 - fv), (iv1, fv)):
+        for (iu, wu) in ((iu0, 1.0 - fu), (iu1, fu)):
+            w = wv[:, None] * wu[None, :]
+            eout += w[None, :, :, None] * env[:, iv][:, :, iu]
+    return np.concatenate([out.reshape(-1), eout.reshape(-1)])
+
+
 def gn_step(scene: OracleScene, x: np.ndarray, targets: np.ndarray, precond: str = "jacobi", max_iters: int = 20,
             rel_tol: float = 0.0, abs_eps: float = 0.0, stall_ratio: float = 0.0, line_search_on: bool = True,
             ls_factor: float = 0.7, ls_max: int = 20, learned_minv=None):

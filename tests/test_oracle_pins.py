@@ -495,3 +495,86 @@ def test_gauss_newton_converges_near_ground_truth(oracle_mod):
         x = out["x"]
     Fs.append(sc.render(x, targets)[2])
     assert Fs[-1] < 1e-6 * Fs[0], Fs
+
+
+# ------------------------------------------------------------------ hierarchy (Sec. IV)
+
+def _half_spec(spec):
+    import dataclasses
+    return dataclasses.replace(spec, nx=spec.nx // 2, ny=spec.ny // 2, nz=spec.nz // 2,
+                               env_w=spec.env_w // 2, env_h=spec.env_h // 2)
+
+
+def test_upsample_constant_field_and_sigma_scale(oracle_mod):
+    """A constant grid stays constant; sigma halves with the voxel side (optical depth per
+    voxel length), colours and texel opacities do not change."""
+    fine = ps.SceneSpec(8, 6, 4, bbox_min=(-1, -0.75, -0.5), bbox_max=(1, 0.75, 0.5), layer_radii=(1.8, 3.0),
+                        env_w=16, env_h=8)
+    coarse = _half_spec(fine)
+    x = ps.init_params(coarse, colour=0.3, sigma=0.8, alpha=0.25).astype(np.float64)
+    y = oracle_mod.upsample(coarse, x, fine).reshape(-1, 4)
+    nv = fine.n_vox
+    c, sg, al = (float(np.float32(v)) for v in (0.3, 0.8, 0.25))  # the packed parameters are float32
+    np.testing.assert_allclose(y[:nv, :3], c, rtol=1e-12)
+    np.testing.assert_allclose(y[:nv, 3], 0.5 * sg, rtol=1e-12)
+    np.testing.assert_allclose(y[nv:, :3], c, rtol=1e-12)
+    np.testing.assert_allclose(y[nv:, 3], al, rtol=1e-12)
+    assert y.shape[0] == fine.n_units
+
+
+def test_upsample_reproduces_affine_fields_inside(oracle_mod):
+    """Trilinear / bilinear interpolation is exact on affine functions of the cell-centre
+    position, away from the clamped border cells (and along the periodic azimuth for a
+    field periodic in it)."""
+    coarse = ps.SceneSpec(6, 6, 6, layer_radii=(1.8,), env_w=12, env_h=6)
+    fine = ps.SceneSpec(12, 12, 12, layer_radii=(1.8,), env_w=24, env_h=12)
+    def centres(n):
+        return -1.0 + (np.arange(n) + 0.5) * 2.0 / n
+    zc, yc, xc = np.meshgrid(centres(6), centres(6), centres(6), indexing="ij")
+    g = np.zeros((6, 6, 6, 4))
+    g[..., 0] = 0.3 + 0.2 * xc - 0.1 * yc + 0.05 * zc
+    g[..., 3] = 2.0 + xc + yc - zc
+    vc = (np.arange(6) + 0.5) / 6.0
+    e = np.zeros((1, 6, 12, 4))
+    e[..., 1] = (0.2 + 0.5 * vc)[None, :, None]     # affine in the polar coordinate
+    e[..., 2] = 0.7                                  # constant (and so periodic) in azimuth
+    x = np.concatenate([g.reshape(-1), e.reshape(-1)])
+    y = oracle_mod.upsample(coarse, x, fine)
+    gy = y[:4 * fine.n_vox].reshape(12, 12, 12, 4)
+    Z, Y, X = np.meshgrid(centres(12), centres(12), centres(12), indexing="ij")
+    inner = (slice(1, 11),) * 3
+    np.testing.assert_allclose(gy[..., 0][inner], (0.3 + 0.2 * X - 0.1 * Y + 0.05 * Z)[inner], atol=1e-12)
+    np.testing.assert_allclose(gy[..., 3][inner], 0.5 * (2.0 + X + Y - Z)[inner], atol=1e-12)
+    ey = y[4 * fine.n_vox:].reshape(1, 12, 24, 4)
+    v = (np.arange(12) + 0.5) / 12.0
+    np.testing.assert_allclose(ey[0, 1:11, :, 1], np.broadcast_to((0.2 + 0.5 * v)[1:11, None], (10, 24)), atol=1e-12)
+    np.testing.assert_allclose(ey[..., 2], 0.7, atol=1e-12)
+
+
+def test_upsample_wraps_in_azimuth(oracle_mod):
+    """The first and last destination texel columns interpolate between the last and first
+    source columns (periodic azimuth), equally weighted at the seam."""
+    coarse = ps.SceneSpec(2, 2, 2, layer_radii=(1.8,), env_w=4, env_h=2)
+    fine = ps.SceneSpec(4, 4, 4, layer_radii=(1.8,), env_w=8, env_h=4)
+    e = np.zeros((1, 2, 4, 4))
+    e[0, :, :, 0] = np.array([1.0, 2.0, 3.0, 4.0])[None, :]
+    x = np.concatenate([np.zeros(4 * 8), e.reshape(-1)])
+    y = oracle_mod.upsample(coarse, x, fine)[4 * fine.n_vox:].reshape(1, 4, 8, 4)
+    # destination column j sits at source coordinate (j + 0.5) / 2 - 0.5
+    np.testing.assert_allclose(y[0, 0, :, 0], [0.75 * 1 + 0.25 * 4, 0.75 * 1 + 0.25 * 2, 0.25 * 1 + 0.75 * 2,
+                                               0.75 * 2 + 0.25 * 3, 0.25 * 2 + 0.75 * 3, 0.75 * 3 + 0.25 * 4,
+                                               0.25 * 3 + 0.75 * 4, 0.75 * 4 + 0.25 * 1], atol=1e-12)
+
+
+def test_upsampled_uniform_medium_renders_the_same(oracle_mod):
+    """Closed form: in a uniform medium a ray's transmittance is exp(-sigma_vox * L_vox).
+    Refining the grid doubles L in voxel units and the upsampling halves sigma, so every
+    rendered pixel is unchanged."""
+    coarse = ps.SceneSpec(8, 8, 8, layer_radii=(1.8,), env_w=16, env_h=8)
+    fine = ps.SceneSpec(16, 16, 16, layer_radii=(1.8,), env_w=32, env_h=16)
+    cams = ps.make_cameras("sphere", 3, 9, 7, 40.0, 3.0, np.random.default_rng(4))
+    x = ps.init_params(coarse, colour=0.6, sigma=0.35, alpha=0.9).astype(np.float64)
+    y = oracle_mod.upsample(coarse, x, fine)
+    Hc = oracle_mod.OracleScene(coarse, cams).render(x)[0]
+    Hf = oracle_mod.OracleScene(fine, cams).render(y)[0]
+    np.testing.assert_allclose(Hf, Hc, rtol=1e-9, atol=1e-12)
