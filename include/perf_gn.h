@@ -207,6 +207,21 @@ int32_t perf_objective(perf_scene* s, const float* d_x, const float* d_delta, fl
  */
 int32_t perf_footprint(perf_scene* s, int32_t* d_per_ray, uint64_t* d_totals);
 
+/*
+ * Next hierarchical level (Sec. IV, hierarchical formulation): fill the parameter vector of
+ * level `to` from that of level `from` by linear interpolation at the new cell and texel
+ * centres (trilinear over the grid, clamped at the border; bilinear over each layer,
+ * periodic in azimuth, clamped in polar angle).  sigma is an optical depth per shortest voxel
+ * side, so it is multiplied by side(to) / side(from); colours and texel opacities are
+ * interpolated unchanged.  Any resolution pair is accepted (typically doubled per level).
+ * d_from [4 * units(from)] and d_to [4 * units(to)] are caller-owned FP32 device vectors in
+ * the layout of perf_scene_desc; only the grid/layer sizes, box and radii of the two
+ * descriptors are read.  Errors: PERF_EINVAL if the boxes, layer counts or radii differ or a
+ * pointer is NULL.  Asynchronous on `stream` (a hipStream_t, NULL = default stream).
+ */
+int32_t perf_upsample(const perf_scene_desc* from, const float* d_from, const perf_scene_desc* to, float* d_to,
+                      void* stream);
+
 /* Round FP32 parameters to bfloat16 storage (round to nearest even): d_out[n] uint16. */
 int32_t perf_pack_bf16(const float* d_in, uint16_t* d_out, int64_t n, void* stream);
 

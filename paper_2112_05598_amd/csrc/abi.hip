@@ -346,6 +346,37 @@ int32_t perf_footprint(perf_scene* s, int32_t* d_per_ray, uint64_t* d_totals) {
     return PERF_OK;
 }
 
+int32_t perf_upsample(const perf_scene_desc* from, const float* d_from, const perf_scene_desc* to, float* d_to,
+                      void* stream) {
+    if (!from || !to) return fail(PERF_EINVAL, "null descriptor");
+    if (!d_from || !d_to) return fail(PERF_EINVAL, "null parameter vector");
+    for (const perf_scene_desc* d : {from, to}) {
+        if (d->nx < 2 || d->ny < 2 || d->nz < 2) return fail(PERF_EINVAL, "grid dims must be >= 2");
+        if (d->n_layers < 0 || d->n_layers > PERF_MAX_LAYERS) return fail(PERF_EINVAL, "n_layers must be in 0..8");
+        if (d->n_layers > 0 && (d->env_w < 2 || d->env_h < 2)) return fail(PERF_EINVAL, "env_w and env_h must be >= 2");
+        const int64_t units = (int64_t)d->nx * d->ny * d->nz + (int64_t)d->n_layers * d->env_w * d->env_h;
+        if (units * 10 >= (int64_t)1 << 31) return fail(PERF_EUNSUPPORTED, "too many parameters for 32-bit indexing");
+    }
+    if (from->n_layers != to->n_layers) return fail(PERF_EINVAL, "levels must have the same environment layers");
+    for (int a = 0; a < 3; ++a) {
+        if (from->bbox_min[a] != to->bbox_min[a] || from->bbox_max[a] != to->bbox_max[a])
+            return fail(PERF_EINVAL, "levels must share the bounding box");
+        if (!(from->bbox_max[a] > from->bbox_min[a])) return fail(PERF_EINVAL, "bad bounding box");
+    }
+    for (int l = 0; l < from->n_layers; ++l)
+        if (from->layer_radius[l] != to->layer_radius[l]) return fail(PERF_EINVAL, "levels must share the layer radii");
+    // sigma is an optical depth per shortest voxel side: scale by the ratio of the sides
+    auto side = [](const perf_scene_desc* d) {
+        const float h[3] = {(d->bbox_max[0] - d->bbox_min[0]) / (float)d->nx, (d->bbox_max[1] - d->bbox_min[1]) / (float)d->ny,
+                            (d->bbox_max[2] - d->bbox_min[2]) / (float)d->nz};
+        return fminf(h[0], fminf(h[1], h[2]));
+    };
+    const float scale = side(to) / side(from);
+    CK(launch_upsample(d_from, from->nx, from->ny, from->nz, from->env_w, from->env_h, d_to, to->nx, to->ny, to->nz,
+                       to->env_w, to->env_h, to->n_layers, scale, (hipStream_t)stream));
+    return PERF_OK;
+}
+
 int32_t perf_pack_bf16(const float* d_in, uint16_t* d_out, int64_t n, void* stream) {
     if ((!d_in || !d_out) && n > 0) return fail(PERF_EINVAL, "null argument");
     if (n < 0) return fail(PERF_EINVAL, "negative size");

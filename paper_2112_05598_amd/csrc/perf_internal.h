@@ -119,4 +119,7 @@ hipError_t launch_mlp_infer(const uint16_t* w, const float* feat, const float* b
 hipError_t launch_mlp_train(float* w32, uint16_t* wbf, float* m, float* v, int t, float lr, float damp, const float* feat,
                             const float* blocks, int n, float* loss, float* grad, hipStream_t st);
 
+hipError_t launch_upsample(const float* src, int sx, int sy, int sz, int sw, int sh, float* dst, int dx, int dy,
+                           int dz, int dw, int dh, int layers, float sigma_scale, hipStream_t st);
+
 }  // namespace perf

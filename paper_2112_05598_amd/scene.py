@@ -226,3 +226,22 @@ def mlp_train_step(w32, wbf16, m, v, t: int, lr: float, feat, blocks, loss, grad
     st = ctypes.c_void_p(torch.cuda.current_stream(feat.device).cuda_stream) if stream is None else stream
     abi.check(lib.perf_mlp_train_step(_ptr(w32), _ptr(wbf16), _ptr(m), _ptr(v), int(t), ctypes.c_float(lr), ctypes.c_float(damp),
                                       _ptr(feat), _ptr(blocks), n, _ptr(loss), _ptr(grad), st))
+
+
+def upsample(spec_from, x_from: torch.Tensor, spec_to, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """Parameters of the next hierarchical level from those of the current one (perf_upsample):
+    linear interpolation at the new cell / texel centres, sigma scaled by the voxel-side ratio."""
+    lib = abi.load()
+    n_from = 4 * (spec_from.n_vox + spec_from.n_texels)
+    n_to = 4 * (spec_to.n_vox + spec_to.n_texels)
+    if x_from.dtype != torch.float32 or not x_from.is_cuda or not x_from.is_contiguous() or x_from.numel() != n_from:
+        raise ValueError(f"x_from must be a contiguous float32 device tensor of {n_from} values")
+    if out is None:
+        out = torch.empty(n_to, dtype=torch.float32, device=x_from.device)
+    elif out.dtype != torch.float32 or out.numel() != n_to or not out.is_contiguous():
+        raise ValueError(f"out must be a contiguous float32 tensor of {n_to} values")
+    d_from = make_desc(spec_from, 1, 1)
+    d_to = make_desc(spec_to, 1, 1)
+    st = ctypes.c_void_p(torch.cuda.current_stream(x_from.device).cuda_stream) if stream is None else stream
+    abi.check(lib.perf_upsample(ctypes.byref(d_from), _ptr(x_from), ctypes.byref(d_to), _ptr(out), st))
+    return out

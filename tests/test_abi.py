@@ -113,3 +113,25 @@ def test_product_path_does_not_import_the_oracle():
                 text = open(os.path.join(dirpath, fn)).read()
                 assert "import oracle" not in text and "from oracle" not in text, fn
                 assert "perf_oracle" not in text, fn
+
+
+def test_upsample_rejects_mismatched_levels():
+    """perf_upsample validates the two descriptors before any device work."""
+    import ctypes
+    import perf_synth as ps
+    from paper_2112_05598_amd import abi
+    from paper_2112_05598_amd.scene import make_desc
+    lib = abi.load()
+    a = ps.SceneSpec(8, 8, 8, layer_radii=(1.8,), env_w=16, env_h=8)
+    fake = ctypes.c_void_p(256)  # never dereferenced: every case below fails validation first
+    cases = [
+        (a, ps.SceneSpec(16, 16, 16, bbox_min=(-1, -1, -2), layer_radii=(1.8,), env_w=32, env_h=16)),  # box
+        (a, ps.SceneSpec(16, 16, 16, layer_radii=(1.8, 3.0), env_w=32, env_h=16)),                     # layers
+        (a, ps.SceneSpec(16, 16, 16, layer_radii=(2.0,), env_w=32, env_h=16)),                         # radii
+        (a, ps.SceneSpec(1, 16, 16, layer_radii=(1.8,), env_w=32, env_h=16)),                          # dims
+    ]
+    for sf, st in cases:
+        rc = lib.perf_upsample(ctypes.byref(make_desc(sf, 1, 1)), fake, ctypes.byref(make_desc(st, 1, 1)), fake, None)
+        assert rc == abi.PERF_EINVAL, (sf, st, rc)
+    rc = lib.perf_upsample(ctypes.byref(make_desc(a, 1, 1)), None, ctypes.byref(make_desc(a, 1, 1)), fake, None)
+    assert rc == abi.PERF_EINVAL
