@@ -42,6 +42,7 @@ class _Scene(ctypes.Structure):
         ("bg", ctypes.c_double * 3),
         ("n_cams", ctypes.c_int32), ("width", ctypes.c_int32), ("height", ctypes.c_int32),
         ("cam_origin", ctypes.c_void_p), ("cam_rot", ctypes.c_void_p), ("cam_intr", ctypes.c_void_p),
+        ("aux_lambda", ctypes.c_double),
     ]
 
 
@@ -62,7 +63,7 @@ def _load():
         lib.orc_n_rays.argtypes = [P]
         lib.orc_entry_capacity.restype = i64
         lib.orc_entry_capacity.argtypes = [P]
-        lib.orc_render.argtypes = [P, P, P, P, i64, P, P, P, P]
+        lib.orc_render.argtypes = [P, P, P, P, i64, P, P, P, P, P]
         lib.orc_apply_J.argtypes = [P, P, P, P, i64, P]
         lib.orc_apply_Jt.argtypes = [P, P, P, P, i64, P]
         lib.orc_apply_JtJ.argtypes = [P, P, P, P, i64, P]
@@ -90,9 +91,12 @@ def _f64(a) -> np.ndarray:
 
 
 class OracleScene:
-    """A scene description (grid, environment layers, cameras) for the oracle."""
+    """A scene description (grid, environment layers, cameras) for the oracle.
 
-    def __init__(self, spec, cams):
+    aux_lambda > 0 adds the auxiliary opacity residual of Sec. III-I (Eq. 10) as a fourth
+    residual per ray: residual and J v arrays then have 4 columns, and J^T u takes 4."""
+
+    def __init__(self, spec, cams, aux_lambda: float = 0.0):
         self.lib = _load()
         self.spec = spec
         self.cams = cams
@@ -115,6 +119,9 @@ class OracleScene:
         s.cam_origin = self._origin.ctypes.data
         s.cam_rot = self._rot.ctypes.data
         s.cam_intr = self._intr.ctypes.data
+        s.aux_lambda = float(aux_lambda)
+        self.aux_lambda = float(aux_lambda)
+        self.n_res = 4 if aux_lambda > 0 else 3
         self._s = s
         self.p = ctypes.addressof(s)
         self.n_units = int(self.lib.orc_n_units(self.p))
@@ -139,30 +146,34 @@ class OracleScene:
 
     # ---------------------------------------------------------------- operators
     def render(self, x, targets=None, rays=None):
-        """Eq. 3 per ray: returns (H [n,3], r [n,3] or None, F, T_exit [n])."""
+        """Eq. 3 per ray: returns (H [n,3], r [n,n_res] or None, F, T_exit [n]); with the
+        auxiliary residual on, r[:, 3] is r_4 and F includes it."""
         x = _f64(x)
         r_ids, n = self._rays(rays)
         H = np.zeros((n, 3))
         Te = np.zeros(n)
+        aux = np.zeros(n)
         r = np.zeros((n, 3)) if targets is not None else None
         t = None if targets is None else np.ascontiguousarray(targets, dtype=np.float32).reshape(-1)
         F = ctypes.c_double(0.0)
         self.lib.orc_render(self.p, _ptr(x), _ptr(t), _ptr(r_ids), n, _ptr(H), _ptr(r), ctypes.addressof(F),
-                            _ptr(Te))
+                            _ptr(Te), _ptr(aux))
+        if r is not None and self.n_res == 4:
+            r = np.concatenate([r, aux[:, None]], axis=1)
         return H, r, F.value, Te
 
     def apply_J(self, x, v, rays=None):
         x, v = _f64(x), _f64(v)
         r_ids, n = self._rays(rays)
-        u = np.zeros((n, 3))
+        u = np.zeros((n, self.n_res))
         self.lib.orc_apply_J(self.p, _ptr(x), _ptr(v), _ptr(r_ids), n, _ptr(u))
         return u
 
     def apply_Jt(self, x, u, rays=None):
         x, u = _f64(x), _f64(u).reshape(-1)
         r_ids, n = self._rays(rays)
-        if u.size != 3 * n:
-            raise ValueError("u must have 3 entries per ray")
+        if u.size != self.n_res * n:
+            raise ValueError(f"u must have {self.n_res} entries per ray")
         y = np.zeros(self.n_params)
         self.lib.orc_apply_Jt(self.p, _ptr(x), _ptr(u), _ptr(r_ids), n, _ptr(y))
         return y

@@ -51,6 +51,7 @@ typedef struct {
     const double *cam_origin; /* [n_cams][3] */
     const double *cam_rot;    /* [n_cams][9] row-major, columns right/down/forward */
     const double *cam_intr;   /* [n_cams][4] fx, fy, cx, cy */
+    double aux_lambda;        /* Sec. III-I: weight of the opacity residual, 0 = off */
 } orc_scene;
 
 /* One entry of a ray's Jacobian before merging: parameter unit, dH/dc (same for
@@ -59,12 +60,14 @@ typedef struct {
     int64_t unit;
     double a;
     double s[3];
+    double q;           /* d r_4 / d sigma of the auxiliary residual (0 for texels or when off) */
 } orc_entry;
 
 typedef struct {
     double H[3];
     double T_exit;      /* transmittance through the voxel grid */
     double T_end;       /* transmittance after the last environment layer */
+    double aux;         /* the auxiliary residual r_4 (0 when off) */
     int32_t hit_box;
     int32_t n_layers_hit;
     int64_t n_samples;
@@ -364,6 +367,14 @@ static void orc_row(const orc_scene *s, const double *x, int64_t ray, orc_scratc
     int64_t K = orc_trace(s, x, ray, w->smp, w->lay, Hc, &T_exit, &T_end, &hit, &tfar);
     double dLc[ORC_MAX_LAYERS], dLa[3 * ORC_MAX_LAYERS];
     orc_partials(s, w->smp, K, w->lay, T_exit, mode, w->dHdc, w->dHds, dLc, dLa);
+    /* Sec. III-I (Eq. 10): r_4 = lambda (1 - 4 (T - 1/2)^2) = 4 lambda T (1 - T) with T the
+     * transmittance through the volume, T = exp(-sum_k sigma_k delta_k), so
+     * d r_4 / d sigma_k = 4 lambda (1 - 2T) dT/dsigma_k = -4 lambda (1 - 2T) T delta_k. */
+    double lam = s->aux_lambda, g4 = 0.0, r4 = 0.0;
+    if (lam > 0.0) {
+        r4 = 4.0 * lam * T_exit * (1.0 - T_exit);
+        g4 = -4.0 * lam * (1.0 - 2.0 * T_exit) * T_exit;
+    }
     int64_t n = 0;
     for (int64_t k = 0; k < K; ++k) {
         for (int j = 0; j < 8; ++j) {
@@ -372,6 +383,7 @@ static void orc_row(const orc_scene *s, const double *x, int64_t ray, orc_scratc
             e->unit = w->smp[k].idx[j];
             e->a = wj * w->dHdc[k];
             for (int ch = 0; ch < 3; ++ch) e->s[ch] = wj * w->dHds[3 * k + ch];
+            e->q = wj * g4 * w->smp[k].delta;
         }
     }
     int nl = 0;
@@ -384,6 +396,7 @@ static void orc_row(const orc_scene *s, const double *x, int64_t ray, orc_scratc
             e->unit = w->lay[l].unit[j];
             e->a = wj * dLc[l];
             for (int ch = 0; ch < 3; ++ch) e->s[ch] = wj * dLa[3 * l + ch];
+            e->q = 0.0;
         }
     }
     qsort(w->ent, (size_t)n, sizeof(orc_entry), cmp_entry);
@@ -392,6 +405,7 @@ static void orc_row(const orc_scene *s, const double *x, int64_t ray, orc_scratc
         if (m > 0 && w->ent[m - 1].unit == w->ent[i].unit) {
             w->ent[m - 1].a += w->ent[i].a;
             for (int ch = 0; ch < 3; ++ch) w->ent[m - 1].s[ch] += w->ent[i].s[ch];
+            w->ent[m - 1].q += w->ent[i].q;
         } else {
             w->ent[m++] = w->ent[i];
         }
@@ -401,6 +415,7 @@ static void orc_row(const orc_scene *s, const double *x, int64_t ray, orc_scratc
     for (int ch = 0; ch < 3; ++ch) out->H[ch] = Hc[ch];
     out->T_exit = T_exit;
     out->T_end = T_end;
+    out->aux = r4;
     out->hit_box = hit;
     out->n_layers_hit = nl;
     out->n_samples = K;
@@ -433,9 +448,10 @@ static int orc_tid(void) {
 
 /* Eq. 3 for the listed rays (all rays if rays == NULL): H [n][3], residual
  * r = H - C [n][3] when targets is given (targets indexed by ray id), and the
- * objective F = 0.5 sum r^2 (Eq. 5-6), summed in ray order. */
+ * objective F = 0.5 sum r^2 (Eq. 5-6), summed in ray order.  With the auxiliary
+ * residual on (Sec. III-I), aux_out [n] gets r_4 and F includes 0.5 r_4^2. */
 int orc_render(const orc_scene *s, const double *x, const float *targets, const int64_t *rays,
-               int64_t n, double *H_out, double *r_out, double *F_out, double *T_exit_out) {
+               int64_t n, double *H_out, double *r_out, double *F_out, double *T_exit_out, double *aux_out) {
     double *rr = (double *)calloc((size_t)n, sizeof(double));
     #pragma omp parallel
     {
@@ -454,6 +470,9 @@ int orc_render(const orc_scene *s, const double *x, const float *targets, const 
                 }
             }
             if (T_exit_out) T_exit_out[i] = Te;
+            double r4 = s->aux_lambda > 0.0 ? 4.0 * s->aux_lambda * Te * (1.0 - Te) : 0.0;
+            if (aux_out) aux_out[i] = r4;
+            if (targets) rr[i] += r4 * r4;
         }
         scratch_free(&w);
     }
@@ -464,9 +483,11 @@ int orc_render(const orc_scene *s, const double *x, const float *targets, const 
     return 0;
 }
 
-/* u = J v for the listed rays, u [n][3]. */
+/* u = J v for the listed rays, u [n][nr] with nr = 4 when the auxiliary residual is
+ * on (fourth column d r_4) and 3 otherwise. */
 int orc_apply_J(const orc_scene *s, const double *x, const double *v, const int64_t *rays, int64_t n,
                 double *u) {
+    const int nr = s->aux_lambda > 0.0 ? 4 : 3;
     #pragma omp parallel
     {
         orc_scratch w; scratch_init(s, &w);
@@ -474,13 +495,14 @@ int orc_apply_J(const orc_scene *s, const double *x, const double *v, const int6
         for (int64_t i = 0; i < n; ++i) {
             orc_ray_out ro;
             orc_row(s, x, ray_at(rays, i), &w, 0, &ro);
-            double acc[3] = {0.0, 0.0, 0.0};
+            double acc[4] = {0.0, 0.0, 0.0, 0.0};
             for (int64_t e = 0; e < ro.n_entries; ++e) {
                 const orc_entry *q = &ro.entries[e];
                 const double *vv = v + 4 * q->unit;
                 for (int ch = 0; ch < 3; ++ch) acc[ch] += q->a * vv[ch] + q->s[ch] * vv[3];
+                acc[3] += q->q * vv[3];
             }
-            for (int ch = 0; ch < 3; ++ch) u[3 * i + ch] = acc[ch];
+            for (int ch = 0; ch < nr; ++ch) u[nr * i + ch] = acc[ch];
         }
         scratch_free(&w);
     }
@@ -503,6 +525,7 @@ static void reduce_buffers(double **buf, int nt, int64_t len, double *out) {
 static int orc_adjoint(const orc_scene *s, const double *x, const double *u, const double *v, int jtj,
                        const int64_t *rays, int64_t n, double *y) {
     int64_t P = 4 * orc_units(s);
+    const int nr = s->aux_lambda > 0.0 ? 4 : 3;
     int nt = orc_threads();
     double **buf = (double **)malloc(sizeof(double *) * (size_t)nt);
     for (int t = 0; t < nt; ++t) buf[t] = (double *)calloc((size_t)P, sizeof(double));
@@ -514,22 +537,22 @@ static int orc_adjoint(const orc_scene *s, const double *x, const double *u, con
         for (int64_t i = 0; i < n; ++i) {
             orc_ray_out ro;
             orc_row(s, x, ray_at(rays, i), &w, 0, &ro);
-            double uu[3];
+            double uu[4] = {0.0, 0.0, 0.0, 0.0};
             if (jtj) {
-                uu[0] = uu[1] = uu[2] = 0.0;
                 for (int64_t e = 0; e < ro.n_entries; ++e) {
                     const orc_entry *q = &ro.entries[e];
                     const double *vv = v + 4 * q->unit;
                     for (int ch = 0; ch < 3; ++ch) uu[ch] += q->a * vv[ch] + q->s[ch] * vv[3];
+                    uu[3] += q->q * vv[3];
                 }
             } else {
-                for (int ch = 0; ch < 3; ++ch) uu[ch] = u[3 * i + ch];
+                for (int ch = 0; ch < nr; ++ch) uu[ch] = u[nr * i + ch];
             }
             for (int64_t e = 0; e < ro.n_entries; ++e) {
                 const orc_entry *q = &ro.entries[e];
                 double *yy = yb + 4 * q->unit;
                 for (int ch = 0; ch < 3; ++ch) yy[ch] += q->a * uu[ch];
-                yy[3] += q->s[0] * uu[0] + q->s[1] * uu[1] + q->s[2] * uu[2];
+                yy[3] += q->s[0] * uu[0] + q->s[1] * uu[1] + q->s[2] * uu[2] + q->q * uu[3];
             }
         }
         scratch_free(&w);
@@ -582,15 +605,16 @@ int orc_grad_blocks(const orc_scene *s, const double *x, const float *targets, c
                 r[ch] = ro.H[ch] - (double)targets[3 * ray + ch];
                 rr[i] += r[ch] * r[ch];
             }
+            rr[i] += ro.aux * ro.aux;
             for (int64_t e = 0; e < ro.n_entries; ++e) {
                 const orc_entry *q = &ro.entries[e];
                 double *g = gb + 4 * q->unit;
                 for (int ch = 0; ch < 3; ++ch) g[ch] -= q->a * r[ch];
-                g[3] -= q->s[0] * r[0] + q->s[1] * r[1] + q->s[2] * r[2];
+                g[3] -= q->s[0] * r[0] + q->s[1] * r[1] + q->s[2] * r[2] + q->q * ro.aux;
                 double *b = bb + 5 * q->unit;
                 b[0] += q->a * q->a;
                 for (int ch = 0; ch < 3; ++ch) b[1 + ch] += q->a * q->s[ch];
-                b[4] += q->s[0] * q->s[0] + q->s[1] * q->s[1] + q->s[2] * q->s[2];
+                b[4] += q->s[0] * q->s[0] + q->s[1] * q->s[1] + q->s[2] * q->s[2] + q->q * q->q;
             }
         }
         scratch_free(&w);

@@ -578,3 +578,92 @@ def test_upsampled_uniform_medium_renders_the_same(oracle_mod):
     Hc = oracle_mod.OracleScene(coarse, cams).render(x)[0]
     Hf = oracle_mod.OracleScene(fine, cams).render(y)[0]
     np.testing.assert_allclose(Hf, Hc, rtol=1e-9, atol=1e-12)
+
+
+# ------------------------------------------------------------------ auxiliary opacity residual (Sec. III-I, Eq. 10)
+
+AUX = 0.1
+
+
+@pytest.fixture(scope="module")
+def tiny_aux(oracle_mod, tiny):
+    sc, spec, x, rays = tiny
+    sca = oracle_mod.OracleScene(spec, sc.cams, aux_lambda=AUX)
+    targets = np.random.default_rng(9).uniform(0, 1, (sca.n_rays, 3)).astype(np.float32)
+    return sca, spec, x, rays, targets
+
+
+@pytest.fixture(scope="module")
+def tiny_aux_fd(tiny_aux):
+    """Central differences of all four residuals per ray (r_1..r_3 = H - C, r_4 = Eq. 10)."""
+    sca, spec, x, rays, targets = tiny_aux
+    eps = 1e-6
+    J = np.zeros((4 * len(rays), sca.n_params))
+    for j in range(sca.n_params):
+        xp = x.copy(); xp[j] += eps
+        xm = x.copy(); xm[j] -= eps
+        rp = sca.render(xp, targets, rays=rays)[1].reshape(-1)
+        rm = sca.render(xm, targets, rays=rays)[1].reshape(-1)
+        J[:, j] = (rp - rm) / (2 * eps)
+    return J
+
+
+def test_aux_residual_closed_form(oracle_mod):
+    """Uniform medium: T = e^{-s0 L} with L the chord in voxel lengths, and
+    r_4 = lambda (1 - 4 (T - 1/2)^2); F adds r_4^2 / 2 to the colour residuals."""
+    n = 8
+    spec, cams = axis_scene(n=n, W=5, H=5, fov=10.0)
+    sc = oracle_mod.OracleScene(spec, cams, aux_lambda=AUX)
+    s0 = 0.13
+    x = params(spec, np.r_[0.5, 0.5, 0.5, s0], np.r_[0.2, 0.2, 0.2, 1.0])
+    targets = np.zeros((25, 3), np.float32)
+    H, r, F, Te = sc.render(x, targets)
+    assert r.shape == (25, 4)
+    for ray in range(25):
+        py, px = divmod(ray, 5)
+        dc = np.array([(px + 0.5 - 2.5) / cams.fx[0], (py + 0.5 - 2.5) / cams.fy[0], 1.0])
+        L = 2.0 * np.linalg.norm(dc) / (2.0 / n)
+        T = math.exp(-s0 * L)
+        assert math.isclose(r[ray, 3], AUX * (1.0 - 4.0 * (T - 0.5) ** 2), rel_tol=1e-12)
+    assert math.isclose(F, 0.5 * float((r ** 2).sum()), rel_tol=1e-12)
+    # off: three residuals and no extra term
+    sc0 = oracle_mod.OracleScene(spec, cams)
+    H0, r0, F0, _ = sc0.render(x, targets)
+    assert r0.shape == (25, 3)
+    assert math.isclose(F - F0, 0.5 * float((r[:, 3] ** 2).sum()), rel_tol=1e-12)
+
+
+def test_aux_J_matches_finite_differences(tiny_aux, tiny_aux_fd):
+    sca, spec, x, rays, targets = tiny_aux
+    v = np.random.default_rng(11).normal(size=sca.n_params)
+    u = sca.apply_J(x, v, rays=rays)
+    assert u.shape == (len(rays), 4)
+    ref = (tiny_aux_fd @ v).reshape(-1, 4)
+    assert np.linalg.norm(u - ref) / np.linalg.norm(ref) < 1e-8
+    # the fourth row depends on sigma only
+    aux_rows = tiny_aux_fd[3::4]
+    assert np.abs(aux_rows.reshape(len(rays), -1, 4)[:, :, :3]).max() < 1e-9
+
+
+def test_aux_adjoint_JtJ_and_blocks(tiny_aux, tiny_aux_fd):
+    sca, spec, x, rays, targets = tiny_aux
+    rng = np.random.default_rng(12)
+    u = rng.normal(size=4 * len(rays))
+    y = sca.apply_Jt(x, u, rays=rays)
+    ref = tiny_aux_fd.T @ u
+    assert np.linalg.norm(y - ref) / np.linalg.norm(ref) < 1e-8
+    v = rng.normal(size=sca.n_params)
+    z = sca.apply_JtJ(x, v, rays=rays)
+    refz = tiny_aux_fd.T @ (tiny_aux_fd @ v)
+    assert np.linalg.norm(z - refz) / np.linalg.norm(refz) < 1e-8
+    grad, blocks, F = sca.grad_blocks(x, targets, rays=rays)
+    r = sca.render(x, targets, rays=rays)[1].reshape(-1)
+    np.testing.assert_allclose(grad, -(tiny_aux_fd.T @ r), atol=1e-8 * np.abs(grad).max())
+    assert math.isclose(F, 0.5 * float(r @ r), rel_tol=1e-12)
+    A = tiny_aux_fd.T @ tiny_aux_fd
+    scale = np.abs(A).max()
+    for unit in range(sca.n_units):
+        Bd = A[4 * unit:4 * unit + 4, 4 * unit:4 * unit + 4]
+        b = blocks[unit]
+        exp = np.array([[b[0], 0, 0, b[1]], [0, b[0], 0, b[2]], [0, 0, b[0], b[3]], [b[1], b[2], b[3], b[4]]])
+        assert np.abs(Bd - exp).max() <= 1e-8 * scale
