@@ -85,6 +85,8 @@ def main():
     ap.add_argument("--precond", default="jacobi")
     ap.add_argument("--dtype", default="f32", choices=["f32", "bf16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--aux", type=float, default=0.0,
+                    help="weight of the auxiliary opacity residual (Eq. 10; the paper uses 0.1), 0 = off")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-preconditioner GN run to the Jacobi run's final objective")
     args = ap.parse_args()
@@ -103,13 +105,15 @@ def main():
     w = ps.workload(args.workload)
     print(f"[bench] workload {w.name}: grid {w.spec.nx}^3, {w.spec.n_layers} layers {w.spec.env_w}x{w.spec.env_h}, "
           f"{w.cams.n} cams {w.cams.width}x{w.cams.height}, P={w.spec.n_params}", file=sys.stderr, flush=True)
-    sc = Scene(w.spec, w.cams, None, param_dtype="f32", learned=not args.no_learned, device="cuda:0")
+    sc = Scene(w.spec, w.cams, None, param_dtype="f32", learned=not args.no_learned, device="cuda:0",
+               aux_lambda=args.aux)
     x_gt = torch.from_numpy(w.x_gt).to(dev)
     H, _ = sc.render_residuals(x_gt)           # no targets yet: the render itself
     targets = H.clone()
     sc.set_targets(targets)
     if args.dtype == "bf16":
-        sc = Scene(w.spec, w.cams, targets, param_dtype="bf16", learned=not args.no_learned, device="cuda:0")
+        sc = Scene(w.spec, w.cams, targets, param_dtype="bf16", learned=not args.no_learned, device="cuda:0",
+                   aux_lambda=args.aux)
     _, tot = sc.footprint(per_ray=False)
     tot = tot.cpu().numpy()
     bytes_per_launch = 48.0 * float(tot[0]) + 192.0 * float(tot[1])
@@ -155,7 +159,7 @@ def main():
                                f"{w.spec.env_w}x{w.spec.env_h} at radii {list(w.spec.layer_radii)}, {w.cams.n} cams "
                                f"{w.cams.width}x{w.cams.height} on the upper hemisphere r=4, 40 random spheres/boxes",
                    "rays": sc.n_rays, "params": sc.n_params, "pcg_iters_per_step": args.pcg,
-                   "precond": args.precond, "step_vox": w.spec.step_vox},
+                   "precond": args.precond, "step_vox": w.spec.step_vox, "aux_lambda": args.aux},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_ray<M_JTJ> (J^T J v)", "avg_launch_ms": jtj_ms,

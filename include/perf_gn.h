@@ -93,6 +93,11 @@ typedef struct {
     int32_t width, height;                /* image size shared by every camera */
     int32_t checks;                       /* 1: gn_step checks x / targets for non-finite values */
     int32_t learned;                      /* 1: reserve workspace for the learned preconditioner */
+    float aux_lambda;                     /* Sec. III-I (Eq. 10): weight of the per-ray opacity residual
+                                             r_4 = aux_lambda (1 - 4 (T - 1/2)^2), T the transmittance
+                                             through the volume (the paper uses 0.1); 0 = off.  When on,
+                                             every ray has n_res = 4 residuals (r, g, b, r_4) instead of
+                                             3 in the residual, J v and J^T u arrays, and F includes r_4^2 / 2 */
 } perf_scene_desc;
 
 typedef struct {
@@ -153,15 +158,18 @@ const char* perf_last_error(void);
 /*
  * Residuals r = H(x) - C per ray (Eq. 3-4, 6) and F = 1/2 sum r^2 (Eq. 5).
  * d_x   device parameters (FP32 or BF16 per param_dtype).
- * d_r   device [rays][3] FP32 output, may be NULL.
+ * d_r   device [rays][n_res] FP32 output (r, g, b and, with aux_lambda > 0, r_4 of Eq. 10),
+ *       may be NULL; a scene without targets writes H [rays][3] instead.
  * d_F   device double[1] output, may be NULL.  Deterministic (no atomics).
  */
 int32_t perf_render_residuals(perf_scene* s, const void* d_x, float* d_r, double* d_F);
 
-/* u = J v, one forward-mode pass per ray (derivative of Eq. 3-4). d_v [P] FP32, d_u [rays][3]. */
+/* u = J v, one forward-mode pass per ray (derivative of Eq. 3-4, and of Eq. 10 when on).
+ * d_v [P] FP32, d_u [rays][n_res]. */
 int32_t perf_apply_J(perf_scene* s, const void* d_x, const float* d_v, float* d_u);
 
-/* y = J^T u, the adjoint pass of Alg. 1 per ray, scattered into y [P] (overwritten). */
+/* y = J^T u, the adjoint pass of Alg. 1 per ray, scattered into y [P] (overwritten).
+ * d_u [rays][n_res]. */
 int32_t perf_apply_Jt(perf_scene* s, const void* d_x, const float* d_u, float* d_y);
 
 /* y = J^T J v = sum_i grad r_i (grad r_i^T v) (Eq. 9), fused per ray; y [P] overwritten. */

@@ -33,6 +33,7 @@ class perf_scene_desc(ctypes.Structure):
         ("width", ctypes.c_int32), ("height", ctypes.c_int32),
         ("checks", ctypes.c_int32),
         ("learned", ctypes.c_int32),
+        ("aux_lambda", ctypes.c_float),
     ]
 
 

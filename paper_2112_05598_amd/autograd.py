@@ -1,6 +1,7 @@
 """render_residuals as a torch.autograd.Function.
 
-forward:  r = H(x) - C per ray (Eq. 3-6), shape [rays, 3], from the library's render pass.
+forward:  r = H(x) - C per ray (Eq. 3-6), shape [rays, 3] (plus the opacity residual of Eq. 10
+          as a fourth column when the scene has it on), from the library's render pass.
 backward: dl/dx = J^T (dl/dr), from the library's adjoint pass, which re-marches every ray
           instead of keeping per-sample state from the forward pass.
 """
@@ -15,7 +16,7 @@ class RenderResiduals(torch.autograd.Function):
         r, _ = scene.render_residuals(x.detach().contiguous())
         ctx.scene = scene
         ctx.save_for_backward(x)
-        return r.view(-1, 3)
+        return r.view(-1, scene.n_res)
 
     @staticmethod
     def backward(ctx, g: torch.Tensor):

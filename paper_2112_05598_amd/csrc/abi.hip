@@ -65,6 +65,7 @@ int32_t validate(const perf_scene_desc* d, int n_cams) {
     if (!(d->step_vox > 0.0f && d->step_vox <= 1.0f)) return fail(PERF_EINVAL, "step_vox must be in (0, 1]");
     if (d->param_dtype != PERF_F32 && d->param_dtype != PERF_BF16) return fail(PERF_EINVAL, "bad param_dtype");
     if (d->width < 1 || d->height < 1) return fail(PERF_EINVAL, "image size must be positive");
+    if (!finite_f(d->aux_lambda) || d->aux_lambda < 0.0f) return fail(PERF_EINVAL, "aux_lambda must be >= 0");
     if (n_cams < 1) return fail(PERF_EINVAL, "need at least one camera");
     double corner = 0.0;
     for (int a = 0; a < 3; ++a) {
@@ -261,10 +262,18 @@ int32_t perf_destroy_scene(perf_scene* s) {
     return PERF_OK;
 }
 
-int32_t perf_render_residuals(perf_scene* s, const void* d_x, float* d_r, double* d_F) {
-    if (!s || !d_x) return fail(PERF_EINVAL, "null scene or parameters");
+// Kernel arguments every ray launch of a scene shares: cameras and the auxiliary residual.
+static RayArgs base_args(const perf_scene* s) {
     RayArgs a{};
     a.cams = s->cams;
+    a.aux = s->desc.aux_lambda;
+    a.nres = s->desc.aux_lambda > 0.0f ? 4 : 3;
+    return a;
+}
+
+int32_t perf_render_residuals(perf_scene* s, const void* d_x, float* d_r, double* d_F) {
+    if (!s || !d_x) return fail(PERF_EINVAL, "null scene or parameters");
+    RayArgs a = base_args(s);
     a.x = d_x;
     a.targets = s->targets;
     a.rout = d_r;
@@ -276,8 +285,7 @@ int32_t perf_render_residuals(perf_scene* s, const void* d_x, float* d_r, double
 
 int32_t perf_apply_J(perf_scene* s, const void* d_x, const float* d_v, float* d_u) {
     if (!s || !d_x || !d_v || !d_u) return fail(PERF_EINVAL, "null argument");
-    RayArgs a{};
-    a.cams = s->cams;
+    RayArgs a = base_args(s);
     a.x = d_x;
     a.v = d_v;
     a.rout = d_u;
@@ -288,8 +296,7 @@ int32_t perf_apply_J(perf_scene* s, const void* d_x, const float* d_v, float* d_
 int32_t perf_apply_Jt(perf_scene* s, const void* d_x, const float* d_u, float* d_y) {
     if (!s || !d_x || !d_u || !d_y) return fail(PERF_EINVAL, "null argument");
     CK(launch_zero(d_y, s->P, s->stream));
-    RayArgs a{};
-    a.cams = s->cams;
+    RayArgs a = base_args(s);
     a.x = d_x;
     a.uin = d_u;
     a.y = d_y;
@@ -300,8 +307,7 @@ int32_t perf_apply_Jt(perf_scene* s, const void* d_x, const float* d_u, float* d
 int32_t perf_apply_JtJ(perf_scene* s, const void* d_x, const float* d_v, float* d_y) {
     if (!s || !d_x || !d_v || !d_y) return fail(PERF_EINVAL, "null argument");
     CK(launch_zero(d_y, s->P, s->stream));
-    RayArgs a{};
-    a.cams = s->cams;
+    RayArgs a = base_args(s);
     a.x = d_x;
     a.v = d_v;
     a.y = d_y;
@@ -312,8 +318,7 @@ int32_t perf_apply_JtJ(perf_scene* s, const void* d_x, const float* d_v, float* 
 static int32_t grad_pass(perf_scene* s, const void* xg, float* grad, float* blocks, bool want_F) {
     if (grad) CK(launch_zero(grad, s->P, s->stream));
     if (blocks) CK(launch_zero(blocks, 5 * s->units, s->stream));
-    RayArgs a{};
-    a.cams = s->cams;
+    RayArgs a = base_args(s);
     a.x = xg;
     a.targets = s->targets;
     a.y = grad;
@@ -388,8 +393,7 @@ int32_t perf_pack_bf16(const float* d_in, uint16_t* d_out, int64_t n, void* stre
 // vxt (FP32) and, for BF16 storage, in xb16.
 static int32_t trial_objective(perf_scene* s, const float* d_x, const float* d_delta, float gamma) {
     CK(launch_trial(d_x, d_delta, gamma, s->units, s->geo.nvox, s->vxt, s->xb16, s->stream));
-    RayArgs a{};
-    a.cams = s->cams;
+    RayArgs a = base_args(s);
     a.x = s->xb16 ? (const void*)s->xb16 : (const void*)s->vxt;
     a.targets = s->targets;
     a.partials = s->partials;
@@ -534,8 +538,7 @@ int32_t perf_gn_step(perf_scene* s, float* d_x, const perf_pcg_opts* opts, perf_
     const bool poll = opts->rel_tol > 0.0 || opts->abs_eps > 0.0 || opts->stall_ratio > 0.0;
     for (int it = 0; it < opts->max_iters; ++it) {
         CK(launch_zero(s->vAp, s->P, st, s->iflags + I_DONE));
-        RayArgs a{};
-        a.cams = s->cams;
+        RayArgs a = base_args(s);
         a.x = xg;
         a.v = s->vp;
         a.y = s->vAp;

@@ -77,13 +77,15 @@ struct RayArgs {
     const void* x;           // params (FP32 float4 or BF16 ushort4 per unit)
     const float* v;          // tangent [P] (JVP / JTJ)
     const float* targets;    // [rays][3] (RENDER residuals / GRAD)
-    const float* uin;        // [rays][3] (VJP)
-    float* rout;             // [rays][3] residuals (RENDER) or u (JVP)
+    const float* uin;        // [rays][nres] (VJP)
+    float* rout;             // [rays][nres] residuals (RENDER with targets) or u (JVP); [rays][3] H otherwise
     float* y;                // [P] scatter target (VJP / JTJ), gradient (GRAD), feature sums (FEAT)
     float* blocks;           // [units][5] (GRAD)
     double* partials;        // [n_tiles] FP64 sums of r^2
     const int* done;         // skip the launch's work when *done != 0 (PCG stop on device)
     int32_t* footprint;      // [rays][2] (M_FEAT footprint mode)
+    float aux;               // weight lambda of the auxiliary opacity residual (Sec. III-I), 0 = off
+    int nres;                // residuals per ray: 4 with the auxiliary residual, else 3
 };
 
 hipError_t launch_ray(int mode, int param_dtype, const Geo& g, const RayArgs& a, hipStream_t st);

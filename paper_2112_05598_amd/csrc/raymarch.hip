@@ -733,7 +733,7 @@ __device__ __forceinline__ void gather(XL<PD> X, const Corners& c, int nx, int n
 // Every lane still takes its own samples in its own order; only their timing changes.
 template <int PD, bool TAN>
 __device__ __forceinline__ void forward(const Geo& G, const Ray& r, bool live, XL<PD> X, const float4* __restrict__ V,
-                                        float H[3], float& Texit, float Hd[3], Depth& depth) {
+                                        float H[3], float& Texit, float& Tdexit, float Hd[3], Depth& depth) {
     float T = 1.0f, Td = 0.0f;
     depth.s = 0.0f;
     depth.c = 0.0f;
@@ -783,6 +783,7 @@ __device__ __forceinline__ void forward(const Geo& G, const Ray& r, bool live, X
         T *= e;
     }
     Texit = T;
+    Tdexit = Td;
     if (!live) return;
     const float tmin = r.hit ? r.tf : 0.0f;
     for (int l = 0; l < G.n_layers; ++l) {
@@ -884,7 +885,8 @@ __device__ __forceinline__ void env_back(const Geo& G, const Ray& r, XL<PD> X, f
 // and T_k = exp(-V_k) with V_k the compensated optical depth stepped back.
 template <int PD>
 __device__ __forceinline__ void adjoint_scatter(const Geo& G, const Ray& r, bool live, XL<PD> X, const float u[3],
-                                                Depth depth, Brick4& B, TexTable<4>& TT, float* __restrict__ y) {
+                                                float q4, Depth depth, Brick4& B, TexTable<4>& TT,
+                                                float* __restrict__ y) {
     SinkY sink{y};
     const float Tx = exp_neg(depth.value());
     float uE = 0.0f;
@@ -941,7 +943,7 @@ __device__ __forceinline__ void adjoint_scatter(const Geo& G, const Ray& r, bool
             const float al = one_minus_exp_neg(tau, exp_neg(tau));
             const float A = T * al;
             const float uc = u[0] * c0 + u[1] * c1 + u[2] * c2;
-            const float ds = dk * (Tn * uc - uG);
+            const float ds = dk * (Tn * uc - uG + q4);
             uG += A * uc;
             Tn = T;
             val = f4{A * u[0], A * u[1], A * u[2], ds};
@@ -960,8 +962,8 @@ __device__ __forceinline__ void adjoint_scatter(const Geo& G, const Ray& r, bool
 // the slot of the one that left and nothing moves.  The flushed per-ray products
 // (gradient and block entries, linear in the rays) are combined per wave in LDS.
 struct GradWin {
-    int i[3];                          // low corner of the window
-    float a[8], s0[8], s1[8], s2[8];   // per slot: sum w A and sum w d_sigma (3 colours)
+    int i[3];                                 // low corner of the window
+    float a[8], s0[8], s1[8], s2[8], s3[8];   // per slot: sum w A, sum w d_sigma (3 colours), sum w delta
 };
 
 // slots whose voxel leaves when the window's low corner moves from w to c (at most one cell
@@ -982,7 +984,7 @@ __device__ __forceinline__ unsigned leaving_slots(const int w[3], const int c[3]
 
 template <int SLOT>
 __device__ __forceinline__ void grad_flush_slot(const Geo& G, unsigned pend, const GradWin& w, const float rr[3],
-                                                BrickAtomic<9>& B, const SinkGrad& sink) {
+                                                float r4, float g4, BrickAtomic<9>& B, const SinkGrad& sink) {
     const bool mine = (pend >> SLOT) & 1u;
     if (!wave_any(mine)) return;
     if (!mine) return;
@@ -990,31 +992,32 @@ __device__ __forceinline__ void grad_flush_slot(const Geo& G, unsigned pend, con
     const int y = w.i[1] + (((SLOT >> 1) ^ w.i[1]) & 1);
     const int z = w.i[2] + (((SLOT >> 2) ^ w.i[2]) & 1);
     const float a = w.a[SLOT], s0 = w.s0[SLOT], s1 = w.s1[SLOT], s2 = w.s2[SLOT];
-    const float v[9] = {-a * rr[0], -a * rr[1], -a * rr[2], -(s0 * rr[0] + s1 * rr[1] + s2 * rr[2]),
+    const float q = g4 * w.s3[SLOT];  // the auxiliary residual's sigma partial (0 when off)
+    const float v[9] = {-a * rr[0], -a * rr[1], -a * rr[2], -(s0 * rr[0] + s1 * rr[1] + s2 * rr[2] + q * r4),
                         a * a,      a * s0,     a * s1,     a * s2,
-                        s0 * s0 + s1 * s1 + s2 * s2};
+                        s0 * s0 + s1 * s1 + s2 * s2 + q * q};
     const int lo[3] = {x, y, z};
     if (B.inside(lo, lo)) B.add(x, y, z, v);
     else sink((z * G.ny + y) * G.nx + x, v);
 }
 
-__device__ __forceinline__ void grad_flush(const Geo& G, unsigned pend, GradWin& w, const float rr[3], BrickAtomic<9>& B,
-                                           const SinkGrad& sink) {
-    grad_flush_slot<0>(G, pend, w, rr, B, sink);
-    grad_flush_slot<1>(G, pend, w, rr, B, sink);
-    grad_flush_slot<2>(G, pend, w, rr, B, sink);
-    grad_flush_slot<3>(G, pend, w, rr, B, sink);
-    grad_flush_slot<4>(G, pend, w, rr, B, sink);
-    grad_flush_slot<5>(G, pend, w, rr, B, sink);
-    grad_flush_slot<6>(G, pend, w, rr, B, sink);
-    grad_flush_slot<7>(G, pend, w, rr, B, sink);
+__device__ __forceinline__ void grad_flush(const Geo& G, unsigned pend, GradWin& w, const float rr[3], float r4,
+                                           float g4, BrickAtomic<9>& B, const SinkGrad& sink) {
+    grad_flush_slot<0>(G, pend, w, rr, r4, g4, B, sink);
+    grad_flush_slot<1>(G, pend, w, rr, r4, g4, B, sink);
+    grad_flush_slot<2>(G, pend, w, rr, r4, g4, B, sink);
+    grad_flush_slot<3>(G, pend, w, rr, r4, g4, B, sink);
+    grad_flush_slot<4>(G, pend, w, rr, r4, g4, B, sink);
+    grad_flush_slot<5>(G, pend, w, rr, r4, g4, B, sink);
+    grad_flush_slot<6>(G, pend, w, rr, r4, g4, B, sink);
+    grad_flush_slot<7>(G, pend, w, rr, r4, g4, B, sink);
 }
 
 __device__ __forceinline__ unsigned nonzero_slots(const GradWin& w) {
     unsigned m = 0u;
 #pragma unroll
     for (int b = 0; b < 8; ++b)
-        if (w.a[b] != 0.0f || w.s0[b] != 0.0f || w.s1[b] != 0.0f || w.s2[b] != 0.0f) m |= 1u << b;
+        if (w.a[b] != 0.0f || w.s0[b] != 0.0f || w.s1[b] != 0.0f || w.s2[b] != 0.0f || w.s3[b] != 0.0f) m |= 1u << b;
     return m;
 }
 
@@ -1022,14 +1025,15 @@ __device__ __forceinline__ void clear_slots(GradWin& w, unsigned m) {
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
         if (m & (1u << b)) {
-            w.a[b] = 0.0f; w.s0[b] = 0.0f; w.s1[b] = 0.0f; w.s2[b] = 0.0f;
+            w.a[b] = 0.0f; w.s0[b] = 0.0f; w.s1[b] = 0.0f; w.s2[b] = 0.0f; w.s3[b] = 0.0f;
         }
     }
 }
 
 template <int PD>
 __device__ __forceinline__ void grad_scatter(const Geo& G, const Ray& r, bool live, XL<PD> X, const float rr[3],
-                                             Depth depth, BrickAtomic<9>& B, TexTable<9>& TT, float* __restrict__ grad,
+                                             float r4, float g4, Depth depth, BrickAtomic<9>& B, TexTable<9>& TT,
+                                             float* __restrict__ grad,
                                              float* __restrict__ blocks) {
     SinkGrad sink{grad, blocks};
     const float Tx = exp_neg(depth.value());
@@ -1090,7 +1094,7 @@ __device__ __forceinline__ void grad_scatter(const Geo& G, const Ray& r, bool li
         if (ended) pend = 0xFFu;
         else if (on && started) pend = leaving_slots(w.i, c.i);
         if (pend) pend &= nonzero_slots(w);
-        grad_flush(G, pend, w, rr, B, sink);
+        grad_flush(G, pend, w, rr, r4, g4, B, sink);
         if (ended) {
             clear_slots(w, 0xFFu);
             ended = false;
@@ -1130,6 +1134,7 @@ __device__ __forceinline__ void grad_scatter(const Geo& G, const Ray& r, bool li
             w.s0[b] += wb * ds0;
             w.s1[b] += wb * ds1;
             w.s2[b] += wb * ds2;
+            w.s3[b] += wb * dk;
         }
         if (k == 0) ended = true;
     }
@@ -1138,7 +1143,7 @@ __device__ __forceinline__ void grad_scatter(const Geo& G, const Ray& r, bool li
         const int lo[3] = {w.i[0], w.i[1], w.i[2]}, hi[3] = {w.i[0] + 1, w.i[1] + 1, w.i[2] + 1};
         B.fit(G, ended, lo, hi, sink);
         unsigned pend = ended ? nonzero_slots(w) : 0u;
-        grad_flush(G, pend, w, rr, B, sink);
+        grad_flush(G, pend, w, rr, r4, g4, B, sink);
     }
     B.flush_all(G, sink);
 }
@@ -1275,13 +1280,19 @@ __global__ __launch_bounds__(kBlock) void k_ray(Geo G, RayArgs A) {
         r.K = 0;
         r.hit = false;
     }
-    float H[3], Hd[3], Texit;
+    float H[3], Hd[3], Texit, Tdexit;
     Depth depth;
     if constexpr (MODE == M_JVP || MODE == M_JTJ) {
-        forward<PD, true>(G, r, p.active, X, reinterpret_cast<const float4*>(A.v), H, Texit, Hd, depth);
+        forward<PD, true>(G, r, p.active, X, reinterpret_cast<const float4*>(A.v), H, Texit, Tdexit, Hd, depth);
     } else {
-        forward<PD, false>(G, r, p.active, X, nullptr, H, Texit, Hd, depth);
+        forward<PD, false>(G, r, p.active, X, nullptr, H, Texit, Tdexit, Hd, depth);
     }
+    // auxiliary opacity residual (Sec. III-I, Eq. 10): r4 = lambda (1 - 4 (T - 1/2)^2) =
+    // 4 lambda T (1 - T) with T the transmittance through the volume; dr4/dT = 4 lambda (1 - 2T)
+    const bool aux = A.aux > 0.0f;
+    const float r4 = aux ? 4.0f * A.aux * Texit * (1.0f - Texit) : 0.0f;
+    const float dr4 = aux ? 4.0f * A.aux * (1.0f - 2.0f * Texit) : 0.0f;
+    const int nres = A.nres;
     double rr_sum = 0.0;
     if constexpr (MODE == M_RENDER) {
         if (p.active) {
@@ -1292,9 +1303,11 @@ __global__ __launch_bounds__(kBlock) void k_ray(Geo G, RayArgs A) {
                     res[ch] = H[ch] - A.targets[3 * p.ray + ch];
                     rr_sum += (double)res[ch] * (double)res[ch];
                 }
+                rr_sum += (double)r4 * (double)r4;
                 if (A.rout) {
 #pragma unroll
-                    for (int ch = 0; ch < 3; ++ch) A.rout[3 * p.ray + ch] = res[ch];
+                    for (int ch = 0; ch < 3; ++ch) A.rout[nres * p.ray + ch] = res[ch];
+                    if (aux) A.rout[nres * p.ray + 3] = r4;
                 }
             } else if (A.rout) {
 #pragma unroll
@@ -1304,7 +1317,8 @@ __global__ __launch_bounds__(kBlock) void k_ray(Geo G, RayArgs A) {
     } else if constexpr (MODE == M_JVP) {
         if (p.active) {
 #pragma unroll
-            for (int ch = 0; ch < 3; ++ch) A.rout[3 * p.ray + ch] = Hd[ch];
+            for (int ch = 0; ch < 3; ++ch) A.rout[nres * p.ray + ch] = Hd[ch];
+            if (aux) A.rout[nres * p.ray + 3] = dr4 * Tdexit;  // d r4 = dr4/dT * dT
         }
     } else if constexpr (SCATTER) {
         TexTable<NCH> TT;
@@ -1313,18 +1327,24 @@ __global__ __launch_bounds__(kBlock) void k_ray(Geo G, RayArgs A) {
             Brick4 B;
             B.init(s_brick4 + wave * kB3, s_tag + wave * kB3);
             float u[3] = {0.0f, 0.0f, 0.0f};
+            float u4 = 0.0f;
             if (p.active) {
                 if constexpr (MODE == M_VJP) {
-                    u[0] = A.uin[3 * p.ray];
-                    u[1] = A.uin[3 * p.ray + 1];
-                    u[2] = A.uin[3 * p.ray + 2];
+                    u[0] = A.uin[nres * p.ray];
+                    u[1] = A.uin[nres * p.ray + 1];
+                    u[2] = A.uin[nres * p.ray + 2];
+                    if (aux) u4 = A.uin[nres * p.ray + 3];
                 } else {
                     u[0] = Hd[0];
                     u[1] = Hd[1];
                     u[2] = Hd[2];
+                    u4 = dr4 * Tdexit;
                 }
             }
-            adjoint_scatter<PD>(G, r, p.active, X, u, depth, B, TT, A.y);
+            // u4 d r4 / d sigma_k = u4 dr4/dT (-T delta_k): a per-ray constant times delta_k,
+            // added to the sigma partial of every sample
+            const float q4 = -u4 * dr4 * Texit;
+            adjoint_scatter<PD>(G, r, p.active, X, u, q4, depth, B, TT, A.y);
         } else if constexpr (MODE == M_GRAD) {
             BrickAtomic<NCH> B;
             B.init((float*)(s_brick + wave * NCH * kB3 / 4));
@@ -1335,8 +1355,11 @@ __global__ __launch_bounds__(kBlock) void k_ray(Geo G, RayArgs A) {
                     res[ch] = H[ch] - A.targets[3 * p.ray + ch];
                     rr_sum += (double)res[ch] * (double)res[ch];
                 }
+                rr_sum += (double)r4 * (double)r4;
             }
-            grad_scatter<PD>(G, r, p.active, X, res, depth, B, TT, A.y, A.blocks);
+            // the auxiliary residual's row: d r4 / d sigma_k = g4 delta_k
+            const float g4 = -dr4 * Texit;
+            grad_scatter<PD>(G, r, p.active, X, res, p.active ? r4 : 0.0f, g4, depth, B, TT, A.y, A.blocks);
         } else {
             Brick<NCH> B;
             B.init(s_brick + wave * NCH * kB3 / 4, s_tag + wave * kB3);

@@ -19,7 +19,7 @@ def _ptr(t: Optional[torch.Tensor]):
 
 
 def make_desc(spec, width: int, height: int, param_dtype: str = "f32", checks: bool = False,
-              learned: bool = False) -> abi.perf_scene_desc:
+              learned: bool = False, aux_lambda: float = 0.0) -> abi.perf_scene_desc:
     d = abi.perf_scene_desc()
     d.nx, d.ny, d.nz = spec.nx, spec.ny, spec.nz
     for i in range(3):
@@ -35,6 +35,7 @@ def make_desc(spec, width: int, height: int, param_dtype: str = "f32", checks: b
     d.width, d.height = width, height
     d.checks = 1 if checks else 0
     d.learned = 1 if learned else 0
+    d.aux_lambda = aux_lambda
     return d
 
 
@@ -52,15 +53,20 @@ def make_cameras(cams) -> ctypes.Array:
 
 
 class Scene:
-    """A grid + environment layers + posed images living on one GPU."""
+    """A grid + environment layers + posed images living on one GPU.
+
+    aux_lambda > 0 turns on the per-ray opacity residual of Sec. III-I (Eq. 10): residual, J v and
+    J^T u vectors then hold n_res = 4 values per ray instead of 3."""
 
     def __init__(self, spec, cams, targets: Optional[torch.Tensor] = None, param_dtype: str = "f32",
-                 checks: bool = False, learned: bool = False, device: str = "cuda"):
+                 checks: bool = False, learned: bool = False, device: str = "cuda", aux_lambda: float = 0.0):
         self.lib = abi.load()
         self.spec = spec
         self.device = torch.device(device)
         self.param_dtype = param_dtype
-        self.desc = make_desc(spec, cams.width, cams.height, param_dtype, checks, learned)
+        self.desc = make_desc(spec, cams.width, cams.height, param_dtype, checks, learned, aux_lambda)
+        self.aux_lambda = float(aux_lambda)
+        self.n_res = 4 if aux_lambda > 0 else 3
         self._cams = make_cameras(cams)
         n = cams.n
         nbytes = int(self.lib.perf_workspace_bytes(ctypes.byref(self.desc), n))
@@ -116,7 +122,8 @@ class Scene:
     def render_residuals(self, x: torch.Tensor, want_r: bool = True):
         self._check_params(x)
         self._bind()
-        r = torch.empty(self.n_rays * 3, dtype=torch.float32, device=self.device) if want_r else None
+        per = self.n_res if self._targets is not None else 3
+        r = torch.empty(self.n_rays * per, dtype=torch.float32, device=self.device) if want_r else None
         F = torch.zeros(1, dtype=torch.float64, device=self.device)
         abi.check(self.lib.perf_render_residuals(self.handle, _ptr(x), _ptr(r), _ptr(F)))
         return r, F
@@ -125,13 +132,15 @@ class Scene:
         self._check_params(x)
         self._vec(v, self.n_params, "v")
         self._bind()
-        u = out if out is not None else torch.empty(self.n_rays * 3, dtype=torch.float32, device=self.device)
+        if out is not None:
+            self._vec(out, self.n_res * self.n_rays, "out")
+        u = out if out is not None else torch.empty(self.n_rays * self.n_res, dtype=torch.float32, device=self.device)
         abi.check(self.lib.perf_apply_J(self.handle, _ptr(x), _ptr(v), _ptr(u)))
         return u
 
     def apply_Jt(self, x, u, out=None):
         self._check_params(x)
-        self._vec(u, 3 * self.n_rays, "u")
+        self._vec(u, self.n_res * self.n_rays, "u")
         self._bind()
         y = out if out is not None else torch.empty(self.n_params, dtype=torch.float32, device=self.device)
         abi.check(self.lib.perf_apply_Jt(self.handle, _ptr(x), _ptr(u), _ptr(y)))

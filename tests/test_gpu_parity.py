@@ -24,18 +24,18 @@ def rel(a, b):
 
 
 class Case:
-    def __init__(self, name, background=(0.0, 0.0, 0.0), x_kind="init", seed=0):
+    def __init__(self, name, background=(0.0, 0.0, 0.0), x_kind="init", seed=0, aux=0.0):
         import oracle
         from paper_2112_05598_amd.scene import Scene
-        print(f"[case] {name} x={x_kind} bg={background}", flush=True)
+        print(f"[case] {name} x={x_kind} bg={background} aux={aux}", flush=True)
         w = ps.workload(name)
         self.w = w
         self.spec = dataclasses.replace(w.spec, background=background)
-        self.orc = oracle.OracleScene(self.spec, w.cams)
+        self.orc = oracle.OracleScene(self.spec, w.cams, aux_lambda=aux)
         self.targets = self.orc.render(w.x_gt)[0].astype(np.float32)
         self.dev = torch.device("cuda:0")
         self.t_targets = torch.from_numpy(self.targets.reshape(-1)).to(self.dev)
-        self.sc = Scene(self.spec, w.cams, self.t_targets, device="cuda:0")
+        self.sc = Scene(self.spec, w.cams, self.t_targets, device="cuda:0", aux_lambda=aux)
         if x_kind == "init":
             x = w.x_init.copy()
         elif x_kind == "random":
@@ -55,22 +55,27 @@ class Case:
         self.zero_residual = np.linalg.norm(r) < 1e-3 * np.linalg.norm(H)
 
 
-CASES = [("tiny", (0.0, 0.0, 0.0), "init"), ("tiny", (0.2, 0.3, 0.1), "random"), ("small", (0.0, 0.0, 0.0), "random"),
-         ("ragged", (0.1, 0.1, 0.1), "random"), ("cfg1", (0.0, 0.0, 0.0), "init"), ("cfg1", (0.0, 0.0, 0.0), "gt"),
-         ("ragged", (0.0, 0.0, 0.0), "zero")]
+# (workload, background, parameters, auxiliary-residual weight; the paper's 0.1 where on)
+CASES = [("tiny", (0.0, 0.0, 0.0), "init", 0.0), ("tiny", (0.2, 0.3, 0.1), "random", 0.0),
+         ("small", (0.0, 0.0, 0.0), "random", 0.0), ("ragged", (0.1, 0.1, 0.1), "random", 0.0),
+         ("cfg1", (0.0, 0.0, 0.0), "init", 0.0), ("cfg1", (0.0, 0.0, 0.0), "gt", 0.0),
+         ("ragged", (0.0, 0.0, 0.0), "zero", 0.0),
+         ("small", (0.0, 0.0, 0.0), "random", 0.1), ("ragged", (0.1, 0.1, 0.1), "random", 0.1),
+         ("cfg1", (0.0, 0.0, 0.0), "init", 0.1)]
 
 
-@pytest.fixture(scope="module", params=CASES, ids=lambda c: f"{c[0]}-{c[2]}-bg{c[1][0]}")
+@pytest.fixture(scope="module", params=CASES,
+                ids=lambda c: f"{c[0]}-{c[2]}-bg{c[1][0]}" + (f"-aux{c[3]}" if c[3] else ""))
 def case(request):
-    name, bg, kind = request.param
-    return Case(name, bg, kind)
+    name, bg, kind, aux = request.param
+    return Case(name, bg, kind, aux=aux)
 
 
 def test_render_residuals(case):
     r, F = case.sc.render_residuals(case.tx)
     torch.cuda.synchronize()
     H_or, r_or, F_or, _ = case.orc.render(case.x64, case.targets)
-    r = r.cpu().numpy().reshape(-1, 3)
+    r = r.cpu().numpy().reshape(-1, case.sc.n_res)
     nr, nH = np.linalg.norm(r_or), np.linalg.norm(H_or)
     if nr >= 1e-3 * nH:
         assert rel(r, r_or) <= 1e-5
@@ -96,7 +101,7 @@ def test_apply_J(case):
 
 
 def test_apply_Jt(case):
-    u = ps.random_vector(3 * case.sc.n_rays, 2)
+    u = ps.random_vector(case.sc.n_res * case.sc.n_rays, 2)
     y = case.sc.apply_Jt(case.tx, torch.from_numpy(u).to(case.dev)).cpu().numpy()
     y_or = case.orc.apply_Jt(case.x64, u.astype(np.float64))
     assert rel(y, y_or) <= 1e-4
