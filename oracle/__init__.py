@@ -24,5 +24,6 @@ from .core import (  # noqa: F401
     project,
     gn_step,
     upsample,
+    psnr,
     PCGResult,
 )

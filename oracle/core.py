@@ -77,6 +77,7 @@ def _load():
         lib.orc_sample_field.argtypes = [P, P, P, ctypes.c_int]
         lib.orc_ray.argtypes = [P, i64, P, P]
         lib.orc_feature_sums.argtypes = [P, P, P, i64, P]
+        lib.orc_render_image.argtypes = [P, P, ctypes.c_double, P, P, i64, P, P, P]
         lib.orc_num_threads.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -161,6 +162,19 @@ class OracleScene:
         if r is not None and self.n_res == 4:
             r = np.concatenate([r, aux[:, None]], axis=1)
         return H, r, F.value, Te
+
+    def render_image(self, x, threshold=0.0, targets=None, rays=None):
+        """Rendering of Sec. IV: (H [n,3] with the opacity-threshold rule, T_exit [n], mean
+        squared colour error against targets or None)."""
+        x = _f64(x)
+        r_ids, n = self._rays(rays)
+        H = np.zeros((n, 3))
+        Te = np.zeros(n)
+        t = None if targets is None else np.ascontiguousarray(targets, dtype=np.float32).reshape(-1)
+        mse = ctypes.c_double(0.0)
+        self.lib.orc_render_image(self.p, _ptr(x), float(threshold), _ptr(t), _ptr(r_ids), n, _ptr(H), _ptr(Te),
+                                  ctypes.addressof(mse))
+        return H, Te, (mse.value if targets is not None else None)
 
     def apply_J(self, x, v, rays=None):
         x, v = _f64(x), _f64(v)
@@ -252,6 +266,11 @@ class OracleScene:
 
 
 # ------------------------------------------------------------------ preconditioners (Sec. III-G)
+
+def psnr(mse: float, peak: float = 1.0) -> float:
+    """Peak signal-to-noise ratio in dB of a mean squared error, colours in [0, peak]."""
+    return float(10.0 * np.log10(peak * peak / mse)) if mse > 0 else float("inf")
+
 
 def jacobi_diag(blocks: np.ndarray) -> np.ndarray:
     """diag(J^T J) per parameter from the (d, e, f) blocks: (d, d, d, f) per unit."""

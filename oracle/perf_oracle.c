@@ -216,9 +216,24 @@ typedef struct {
  * Trace one ray with parameters x (P doubles).  Fills the sample list, the
  * layer list and H.  Returns the number of samples.
  */
+static int64_t orc_trace_t(const orc_scene *s, const double *x, int64_t ray, orc_sample *smp,
+                           orc_layer *lay, double H[3], double *T_exit, double *T_end,
+                           int *hit_box, double *t_far, double thresh);
+
 static int64_t orc_trace(const orc_scene *s, const double *x, int64_t ray, orc_sample *smp,
                          orc_layer *lay, double H[3], double *T_exit, double *T_end,
                          int *hit_box, double *t_far) {
+    return orc_trace_t(s, x, ray, smp, lay, H, T_exit, T_end, hit_box, t_far, 0.0);
+}
+
+/*
+ * thresh > 0 is the rendering rule of Sec. IV (rendering): if the volume's total opacity
+ * 1 - T_exit is below thresh, the volume counts as fully transparent (its colour is
+ * dropped and the layers are seen with transmittance 1).  T_exit is still reported.
+ */
+static int64_t orc_trace_t(const orc_scene *s, const double *x, int64_t ray, orc_sample *smp,
+                           orc_layer *lay, double H[3], double *T_exit, double *T_end,
+                           int *hit_box, double *t_far, double thresh) {
     double o[3], d[3], tn = 0.0, tf = 0.0;
     orc_ray(s, ray, o, d);
     *hit_box = orc_slab(s, o, d, &tn, &tf);
@@ -254,6 +269,10 @@ static int64_t orc_trace(const orc_scene *s, const double *x, int64_t ray, orc_s
     }
     *T_exit = T;
     *t_far = *hit_box ? tf : 0.0;
+    if (thresh > 0.0 && 1.0 - T < thresh) {
+        H[0] = H[1] = H[2] = 0.0;
+        T = 1.0;
+    }
     /* environment layers, outward from where the ray leaves the grid */
     double tmin = *hit_box ? tf : 0.0;
     for (int l = 0; l < s->n_layers; ++l) {
@@ -480,6 +499,38 @@ int orc_render(const orc_scene *s, const double *x, const float *targets, const 
     for (int64_t i = 0; i < n; ++i) F += rr[i];
     if (F_out) *F_out = 0.5 * F;
     free(rr);
+    return 0;
+}
+
+/* Rendering of Sec. IV: H [n][3] with the opacity threshold rule (thresh > 0), T_exit [n]
+ * (the volume's transmittance the rule was decided on), and, with targets, the mean squared
+ * colour error over the listed rays (for PSNR). */
+int orc_render_image(const orc_scene *s, const double *x, double thresh, const float *targets,
+                     const int64_t *rays, int64_t n, double *H_out, double *T_exit_out, double *mse_out) {
+    double *se = (double *)calloc((size_t)n, sizeof(double));
+    #pragma omp parallel
+    {
+        orc_scratch w; scratch_init(s, &w);
+        #pragma omp for schedule(dynamic, 64)
+        for (int64_t i = 0; i < n; ++i) {
+            int64_t ray = ray_at(rays, i);
+            double H[3], Te, Tn, tf; int hit;
+            orc_trace_t(s, x, ray, w.smp, w.lay, H, &Te, &Tn, &hit, &tf, thresh);
+            for (int ch = 0; ch < 3; ++ch) {
+                if (H_out) H_out[3 * i + ch] = H[ch];
+                if (targets) {
+                    double r = H[ch] - (double)targets[3 * ray + ch];
+                    se[i] += r * r;
+                }
+            }
+            if (T_exit_out) T_exit_out[i] = Te;
+        }
+        scratch_free(&w);
+    }
+    double acc = 0.0;
+    for (int64_t i = 0; i < n; ++i) acc += se[i];
+    if (mse_out) *mse_out = n > 0 ? acc / (3.0 * (double)n) : 0.0;
+    free(se);
     return 0;
 }
 

@@ -667,3 +667,41 @@ def test_aux_adjoint_JtJ_and_blocks(tiny_aux, tiny_aux_fd):
         b = blocks[unit]
         exp = np.array([[b[0], 0, 0, b[1]], [0, b[0], 0, b[2]], [0, 0, b[0], b[3]], [b[1], b[2], b[3], b[4]]])
         assert np.abs(Bd - exp).max() <= 1e-8 * scale
+
+
+# ------------------------------------------------------------------ rendering with the opacity threshold (Sec. IV)
+
+def test_render_threshold_rule(oracle_mod):
+    """Uniform medium with T = e^{-s0 L}: below the threshold (1 - T < 0.7) the volume is
+    dropped and the pixel shows the opaque layer's colour E; above it, the normal render
+    c0 (1 - T) + T E.  Threshold 0 is the normal render."""
+    n = 8
+    spec, cams = axis_scene(n=n, step=1.0, W=5, H=5, fov=10.0)
+    sc = oracle_mod.OracleScene(spec, cams)
+    c0, E = np.array([0.2, 0.5, 0.9]), np.array([0.6, 0.1, 0.3])
+    for s0, dropped in ((0.01, True), (0.4, False)):
+        x = params(spec, np.r_[c0, s0], np.r_[E, 1.0])
+        H0 = sc.render(x)[0]
+        H, Te, _ = sc.render_image(x, 0.0)
+        np.testing.assert_allclose(H, H0, rtol=1e-14)
+        H7, Te7, _ = sc.render_image(x, 0.7)
+        np.testing.assert_allclose(Te7, Te, rtol=0)
+        assert np.all((1 - Te < 0.7) == dropped)
+        if dropped:
+            np.testing.assert_allclose(H7, np.broadcast_to(E, H7.shape), rtol=1e-14)
+        else:
+            np.testing.assert_allclose(H7, H0, rtol=1e-14)
+
+
+def test_psnr_of_render_against_itself_and_offset(oracle_mod):
+    """MSE is zero against the targets rendered from the same parameters (PSNR infinite up to
+    float32 rounding of the targets) and 10 log10(1 / d^2) for a uniform colour offset d."""
+    spec, cams = axis_scene(n=4, step=1.0, W=6, H=4, fov=20.0)
+    sc = oracle_mod.OracleScene(spec, cams)
+    x = params(spec, np.r_[0.3, 0.4, 0.5, 0.2], np.r_[0.25, 0.25, 0.25, 1.0])
+    H, _, _ = sc.render_image(x, 0.7)
+    _, _, mse = sc.render_image(x, 0.7, targets=H.astype(np.float32))
+    assert mse < 1e-14
+    d = 0.125
+    _, _, mse2 = sc.render_image(x, 0.7, targets=(H + d).astype(np.float32))
+    assert abs(oracle_mod.psnr(mse2) - 10 * np.log10(1 / d ** 2)) < 1e-5
