@@ -98,6 +98,10 @@ typedef struct {
                                              through the volume (the paper uses 0.1); 0 = off.  When on,
                                              every ray has n_res = 4 residuals (r, g, b, r_4) instead of
                                              3 in the residual, J v and J^T u arrays, and F includes r_4^2 / 2 */
+    float render_threshold;               /* Sec. IV (rendering): perf_render_residuals treats the volume
+                                             as fully transparent for rays whose volume opacity 1 - T is
+                                             below this value (the paper uses 0.7 on converged scenes);
+                                             0 = off.  Never applied inside perf_gn_step / perf_objective */
 } perf_scene_desc;
 
 typedef struct {

@@ -34,6 +34,7 @@ class perf_scene_desc(ctypes.Structure):
         ("checks", ctypes.c_int32),
         ("learned", ctypes.c_int32),
         ("aux_lambda", ctypes.c_float),
+        ("render_threshold", ctypes.c_float),
     ]
 
 

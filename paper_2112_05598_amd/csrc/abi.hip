@@ -66,6 +66,8 @@ int32_t validate(const perf_scene_desc* d, int n_cams) {
     if (d->param_dtype != PERF_F32 && d->param_dtype != PERF_BF16) return fail(PERF_EINVAL, "bad param_dtype");
     if (d->width < 1 || d->height < 1) return fail(PERF_EINVAL, "image size must be positive");
     if (!finite_f(d->aux_lambda) || d->aux_lambda < 0.0f) return fail(PERF_EINVAL, "aux_lambda must be >= 0");
+    if (!(d->render_threshold >= 0.0f && d->render_threshold <= 1.0f))
+        return fail(PERF_EINVAL, "render_threshold must be in [0, 1]");
     if (n_cams < 1) return fail(PERF_EINVAL, "need at least one camera");
     double corner = 0.0;
     for (int a = 0; a < 3; ++a) {
@@ -278,6 +280,7 @@ int32_t perf_render_residuals(perf_scene* s, const void* d_x, float* d_r, double
     a.targets = s->targets;
     a.rout = d_r;
     a.partials = d_F ? s->partials : nullptr;
+    a.thresh = s->desc.render_threshold;
     CK(launch_ray(M_RENDER, s->desc.param_dtype, s->geo, a, s->stream));
     if (d_F) CK(launch_sum_partials(s->partials, s->n_ray_blocks, 0.5, d_F, s->stream));
     return PERF_OK;

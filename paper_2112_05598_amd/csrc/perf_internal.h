@@ -86,6 +86,7 @@ struct RayArgs {
     int32_t* footprint;      // [rays][2] (M_FEAT footprint mode)
     float aux;               // weight lambda of the auxiliary opacity residual (Sec. III-I), 0 = off
     int nres;                // residuals per ray: 4 with the auxiliary residual, else 3
+    float thresh;            // RENDER: volume counts as transparent when 1 - T_exit < thresh (0 = off)
 };
 
 hipError_t launch_ray(int mode, int param_dtype, const Geo& g, const RayArgs& a, hipStream_t st);

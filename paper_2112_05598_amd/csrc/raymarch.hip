@@ -733,7 +733,8 @@ __device__ __forceinline__ void gather(XL<PD> X, const Corners& c, int nx, int n
 // Every lane still takes its own samples in its own order; only their timing changes.
 template <int PD, bool TAN>
 __device__ __forceinline__ void forward(const Geo& G, const Ray& r, bool live, XL<PD> X, const float4* __restrict__ V,
-                                        float H[3], float& Texit, float& Tdexit, float Hd[3], Depth& depth) {
+                                        float H[3], float& Texit, float& Tdexit, float Hd[3], Depth& depth,
+                                        float thresh = 0.0f) {
     float T = 1.0f, Td = 0.0f;
     depth.s = 0.0f;
     depth.c = 0.0f;
@@ -784,6 +785,11 @@ __device__ __forceinline__ void forward(const Geo& G, const Ray& r, bool live, X
     }
     Texit = T;
     Tdexit = Td;
+    if (thresh > 0.0f && 1.0f - T < thresh) {
+        // rendering rule (Sec. IV): a volume this transparent counts as empty
+        H[0] = H[1] = H[2] = 0.0f;
+        T = 1.0f;
+    }
     if (!live) return;
     const float tmin = r.hit ? r.tf : 0.0f;
     for (int l = 0; l < G.n_layers; ++l) {
@@ -1285,7 +1291,8 @@ __global__ __launch_bounds__(kBlock) void k_ray(Geo G, RayArgs A) {
     if constexpr (MODE == M_JVP || MODE == M_JTJ) {
         forward<PD, true>(G, r, p.active, X, reinterpret_cast<const float4*>(A.v), H, Texit, Tdexit, Hd, depth);
     } else {
-        forward<PD, false>(G, r, p.active, X, nullptr, H, Texit, Tdexit, Hd, depth);
+        forward<PD, false>(G, r, p.active, X, nullptr, H, Texit, Tdexit, Hd, depth,
+                           MODE == M_RENDER ? A.thresh : 0.0f);
     }
     // auxiliary opacity residual (Sec. III-I, Eq. 10): r4 = lambda (1 - 4 (T - 1/2)^2) =
     // 4 lambda T (1 - T) with T the transmittance through the volume; dr4/dT = 4 lambda (1 - 2T)

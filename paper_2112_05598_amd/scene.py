@@ -19,7 +19,7 @@ def _ptr(t: Optional[torch.Tensor]):
 
 
 def make_desc(spec, width: int, height: int, param_dtype: str = "f32", checks: bool = False,
-              learned: bool = False, aux_lambda: float = 0.0) -> abi.perf_scene_desc:
+              learned: bool = False, aux_lambda: float = 0.0, render_threshold: float = 0.0) -> abi.perf_scene_desc:
     d = abi.perf_scene_desc()
     d.nx, d.ny, d.nz = spec.nx, spec.ny, spec.nz
     for i in range(3):
@@ -36,6 +36,7 @@ def make_desc(spec, width: int, height: int, param_dtype: str = "f32", checks: b
     d.checks = 1 if checks else 0
     d.learned = 1 if learned else 0
     d.aux_lambda = aux_lambda
+    d.render_threshold = render_threshold
     return d
 
 
@@ -56,15 +57,18 @@ class Scene:
     """A grid + environment layers + posed images living on one GPU.
 
     aux_lambda > 0 turns on the per-ray opacity residual of Sec. III-I (Eq. 10): residual, J v and
-    J^T u vectors then hold n_res = 4 values per ray instead of 3."""
+    J^T u vectors then hold n_res = 4 values per ray instead of 3.  render_threshold > 0 applies
+    the rendering rule of Sec. IV in render_residuals (a volume with opacity below it is dropped)."""
 
     def __init__(self, spec, cams, targets: Optional[torch.Tensor] = None, param_dtype: str = "f32",
-                 checks: bool = False, learned: bool = False, device: str = "cuda", aux_lambda: float = 0.0):
+                 checks: bool = False, learned: bool = False, device: str = "cuda", aux_lambda: float = 0.0,
+                 render_threshold: float = 0.0):
         self.lib = abi.load()
         self.spec = spec
         self.device = torch.device(device)
         self.param_dtype = param_dtype
-        self.desc = make_desc(spec, cams.width, cams.height, param_dtype, checks, learned, aux_lambda)
+        self.desc = make_desc(spec, cams.width, cams.height, param_dtype, checks, learned, aux_lambda,
+                              render_threshold)
         self.aux_lambda = float(aux_lambda)
         self.n_res = 4 if aux_lambda > 0 else 3
         self._cams = make_cameras(cams)
