@@ -43,6 +43,7 @@ class _Scene(ctypes.Structure):
         ("n_cams", ctypes.c_int32), ("width", ctypes.c_int32), ("height", ctypes.c_int32),
         ("cam_origin", ctypes.c_void_p), ("cam_rot", ctypes.c_void_p), ("cam_intr", ctypes.c_void_p),
         ("aux_lambda", ctypes.c_double),
+        ("jitter_seed", ctypes.c_uint32),
     ]
 
 
@@ -78,6 +79,8 @@ def _load():
         lib.orc_ray.argtypes = [P, i64, P, P]
         lib.orc_feature_sums.argtypes = [P, P, P, i64, P]
         lib.orc_render_image.argtypes = [P, P, ctypes.c_double, P, P, i64, P, P, P]
+        lib.orc_jitter_u.restype = ctypes.c_double
+        lib.orc_jitter_u.argtypes = [ctypes.c_uint32, i64, ctypes.c_uint32]
         lib.orc_num_threads.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -95,9 +98,10 @@ class OracleScene:
     """A scene description (grid, environment layers, cameras) for the oracle.
 
     aux_lambda > 0 adds the auxiliary opacity residual of Sec. III-I (Eq. 10) as a fourth
-    residual per ray: residual and J v arrays then have 4 columns, and J^T u takes 4."""
+    residual per ray: residual and J v arrays then have 4 columns, and J^T u takes 4.
+    jitter_seed != 0 jitters ray origins within pixels and samples within steps (Sec. IV)."""
 
-    def __init__(self, spec, cams, aux_lambda: float = 0.0):
+    def __init__(self, spec, cams, aux_lambda: float = 0.0, jitter_seed: int = 0):
         self.lib = _load()
         self.spec = spec
         self.cams = cams
@@ -121,6 +125,7 @@ class OracleScene:
         s.cam_rot = self._rot.ctypes.data
         s.cam_intr = self._intr.ctypes.data
         s.aux_lambda = float(aux_lambda)
+        s.jitter_seed = int(jitter_seed) & 0xFFFFFFFF
         self.aux_lambda = float(aux_lambda)
         self.n_res = 4 if aux_lambda > 0 else 3
         self._s = s
@@ -129,6 +134,13 @@ class OracleScene:
         self.n_params = 4 * self.n_units
         self.n_rays = int(self.lib.orc_n_rays(self.p))
         self.n_vox = spec.n_vox
+
+    def set_jitter(self, seed: int):
+        """Jitter seed for every later call (0 = off)."""
+        self._s.jitter_seed = int(seed) & 0xFFFFFFFF
+
+    def jitter_u(self, seed: int, ray: int, stream: int) -> float:
+        return float(self.lib.orc_jitter_u(int(seed) & 0xFFFFFFFF, int(ray), int(stream)))
 
     # ---------------------------------------------------------------- helpers
     def _rays(self, rays):

@@ -52,6 +52,7 @@ typedef struct {
     const double *cam_rot;    /* [n_cams][9] row-major, columns right/down/forward */
     const double *cam_intr;   /* [n_cams][4] fx, fy, cx, cy */
     double aux_lambda;        /* Sec. III-I: weight of the opacity residual, 0 = off */
+    uint32_t jitter_seed;     /* Sec. IV (jittering): 0 = pixel centres and step midpoints */
 } orc_scene;
 
 /* One entry of a ray's Jacobian before merging: parameter unit, dH/dc (same for
@@ -99,7 +100,28 @@ int64_t orc_entry_capacity(const orc_scene *s) {
     return orc_max_samples(s) * 8 + (int64_t)s->n_layers * 4 + 8;
 }
 
-/* Pinhole ray through the centre of pixel (px, py) of camera cam. */
+/*
+ * Jittering (Sec. IV): uniform numbers in [0, 1) from a counter-based generator, the
+ * 32-bit finaliser of MurmurHash3 (Appleby): stream 0 and 1 are a ray's sub-pixel offsets,
+ * stream 2 + k the position of its sample k inside its step.  u = (h >> 8) 2^-24, exact in
+ * single and double precision.  Seed 0 switches jittering off (pixel centre, step midpoint).
+ */
+static uint32_t fmix32(uint32_t h) {
+    h ^= h >> 16;
+    h *= 0x85ebca6bu;
+    h ^= h >> 13;
+    h *= 0xc2b2ae35u;
+    h ^= h >> 16;
+    return h;
+}
+static uint32_t jitter_key(uint32_t seed, int64_t ray) { return fmix32(fmix32(seed) ^ (uint32_t)ray); }
+static double jitter_u(uint32_t key, uint32_t stream) {
+    return (double)(fmix32(key + stream * 0x9e3779b9u) >> 8) * (1.0 / 16777216.0);
+}
+
+double orc_jitter_u(uint32_t seed, int64_t ray, uint32_t stream) { return jitter_u(jitter_key(seed, ray), stream); }
+
+/* Pinhole ray through pixel (px, py) of camera cam: its centre, or a jittered point inside it. */
 void orc_ray(const orc_scene *s, int64_t ray, double o[3], double d[3]) {
     int64_t per_cam = (int64_t)s->width * s->height;
     int64_t cam = ray / per_cam;
@@ -107,7 +129,13 @@ void orc_ray(const orc_scene *s, int64_t ray, double o[3], double d[3]) {
     int64_t py = pix / s->width, px = pix % s->width;
     const double *R = s->cam_rot + 9 * cam;
     const double *K = s->cam_intr + 4 * cam;
-    double dc[3] = {((double)px + 0.5 - K[2]) / K[0], ((double)py + 0.5 - K[3]) / K[1], 1.0};
+    double ox = 0.5, oy = 0.5;
+    if (s->jitter_seed) {
+        uint32_t key = jitter_key(s->jitter_seed, ray);
+        ox = jitter_u(key, 0);
+        oy = jitter_u(key, 1);
+    }
+    double dc[3] = {((double)px + ox - K[2]) / K[0], ((double)py + oy - K[3]) / K[1], 1.0};
     double n = 0.0;
     for (int i = 0; i < 3; ++i) {
         o[i] = s->cam_origin[3 * cam + i];
@@ -241,6 +269,7 @@ static int64_t orc_trace_t(const orc_scene *s, const double *x, int64_t ray, orc
     int64_t K = 0;
     H[0] = H[1] = H[2] = 0.0;
     double T = 1.0;
+    uint32_t jkey = s->jitter_seed ? jitter_key(s->jitter_seed, ray) : 0u;
     if (*hit_box) {
         double L = (tf - tn) / h;              /* chord in voxel lengths */
         K = (int64_t)ceil(L / s->step);
@@ -248,7 +277,10 @@ static int64_t orc_trace_t(const orc_scene *s, const double *x, int64_t ray, orc
             orc_sample *q = &smp[k];
             double dk = L - (double)k * s->step;
             q->delta = dk < s->step ? dk : s->step;     /* shortened last step */
-            double t = tn + h * ((double)k * s->step + 0.5 * q->delta);
+            /* the step's midpoint, or with jittering a uniform point of the step itself
+             * (half a step either side of the midpoint for full steps) */
+            double u = s->jitter_seed ? jitter_u(jkey, (uint32_t)(2 + k)) : 0.5;
+            double t = tn + h * ((double)k * s->step + u * q->delta);
             double p[3] = {o[0] + t * d[0], o[1] + t * d[1], o[2] + t * d[2]};
             orc_trilinear(s, p, q->idx, q->w);
             q->sigma = 0.0;

@@ -705,3 +705,80 @@ def test_psnr_of_render_against_itself_and_offset(oracle_mod):
     d = 0.125
     _, _, mse2 = sc.render_image(x, 0.7, targets=(H + d).astype(np.float32))
     assert abs(oracle_mod.psnr(mse2) - 10 * np.log10(1 / d ** 2)) < 1e-5
+
+
+# ------------------------------------------------------------------ jittering (Sec. IV)
+
+def test_jitter_seed_zero_is_the_plain_render(oracle_mod, tiny):
+    sc, spec, x, rays = tiny
+    j = oracle_mod.OracleScene(spec, sc.cams, jitter_seed=0)
+    np.testing.assert_array_equal(j.render(x, rays=rays)[0], sc.render(x, rays=rays)[0])
+    j.set_jitter(12345)
+    assert np.abs(j.render(x, rays=rays)[0] - sc.render(x, rays=rays)[0]).max() > 1e-6
+
+
+def test_jitter_generator_is_uniform(oracle_mod, tiny):
+    sc = tiny[0]
+    u = np.array([[sc.jitter_u(7, ray, s) for s in range(4)] for ray in range(20000)])
+    assert u.min() >= 0.0 and u.max() < 1.0
+    assert np.all(np.abs(u.mean(0) - 0.5) < 0.01)
+    assert np.all(np.abs(u.var(0) - 1.0 / 12.0) < 0.005)
+    c = np.corrcoef(u.T)
+    assert np.abs(c - np.eye(4)).max() < 0.03
+    # 24-bit values: exact in single precision
+    assert np.all(u * 2 ** 24 == np.round(u * 2 ** 24))
+    # another seed gives other numbers
+    assert abs(sc.jitter_u(8, 0, 0) - sc.jitter_u(7, 0, 0)) > 0
+
+
+def test_jittered_ray_origin_stays_in_its_pixel(oracle_mod):
+    w = ps.workload("small")
+    sc = oracle_mod.OracleScene(w.spec, w.cams, jitter_seed=99)
+    cams = w.cams
+    per = cams.width * cams.height
+    for ray in range(0, sc.n_rays, 97):
+        cam, pix = divmod(ray, per)
+        py, px = divmod(pix, cams.width)
+        o, d = sc.ray(ray)
+        dc = np.asarray(cams.rot[cam]).reshape(3, 3).T @ d  # camera frame (right, down, forward)
+        u = dc[0] / dc[2] * cams.fx[cam] + cams.cx[cam]
+        v = dc[1] / dc[2] * cams.fy[cam] + cams.cy[cam]
+        assert px <= u < px + 1 and py <= v < py + 1, (ray, u, v)
+        assert abs(u - (px + sc.jitter_u(99, ray, 0))) < 1e-9 and abs(v - (py + sc.jitter_u(99, ray, 1))) < 1e-9
+
+
+def test_jittered_samples_stay_in_their_steps(oracle_mod):
+    """With sigma affine in x and a ray along -x, each sample's sigma gives back its
+    position: inside its own step [k D, k D + delta_k), at the midpoint without jitter."""
+    n = 16
+    spec, cams = axis_scene(n=n, step=0.5, W=1, H=1, fov=1.0)
+    h = 2.0 / n
+    centres = -1.0 + (np.arange(n) + 0.5) * h
+    grid = np.zeros((n, n, n, 4))
+    grid[..., 3] = (2.0 + centres)[None, None, :]  # sigma = 2 + x at the cell centres
+    x = pack64(grid, np.zeros((1, spec.env_h, spec.env_w, 4)))
+    for seed in (0, 5, 6):
+        sc = oracle_mod.OracleScene(spec, cams, jitter_seed=seed)
+        smp = sc.ray_samples(x, 0)
+        o, d = sc.ray(0)
+        # the ray enters at x = +1 (d ~ -x); chord coordinate s in voxel lengths
+        xs = smp["sigma"] - 2.0
+        s = (1.0 - xs) / (-d[0]) / h
+        K = len(s)
+        k = np.arange(K)
+        inner = (xs > -1 + h) & (xs < 1 - h)  # away from the clamped border cells
+        lo = k * 0.5
+        assert np.all(s[inner] >= lo[inner] - 1e-9) and np.all(s[inner] < lo[inner] + smp["delta"][inner] + 1e-9)
+        if seed == 0:
+            np.testing.assert_allclose(s[inner], (lo + 0.5 * smp["delta"])[inner], atol=1e-9)
+        else:
+            assert np.abs(s[inner] - (lo + 0.5 * smp["delta"])[inner]).max() > 0.05
+        assert np.all(np.diff(s[inner]) > 0)  # strictly increasing: a voxel that leaves never returns
+
+
+def test_jittered_rows_match_finite_differences(oracle_mod, tiny):
+    sc, spec, x, rays = tiny
+    j = oracle_mod.OracleScene(spec, sc.cams, jitter_seed=31)
+    J = dense_jacobian_rows(j, x, rays)
+    Jfd = dense_jacobian_fd(j, x, rays)
+    assert np.abs(J - Jfd).max() / np.abs(Jfd).max() < 1e-8
