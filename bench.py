@@ -85,6 +85,8 @@ def main():
     ap.add_argument("--precond", default="jacobi")
     ap.add_argument("--dtype", default="f32", choices=["f32", "bf16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--jitter", type=int, default=0,
+                    help="jitter seed base (Sec. IV); each GN step uses base + step index; 0 = off")
     ap.add_argument("--aux", type=float, default=0.0,
                     help="weight of the auxiliary opacity residual (Eq. 10; the paper uses 0.1), 0 = off")
     ap.add_argument("--no-learned", action="store_true",
@@ -122,6 +124,8 @@ def main():
     opts = dict(max_iters=args.pcg, precond=args.precond)
     xw = x0.clone()
     for i in range(args.warmup):
+        if args.jitter:
+            sc.set_jitter(args.jitter + 1000 + i)
         sc.gn_step(xw, **opts)
         print(f"[bench] warmup step {i} done", file=sys.stderr, flush=True)
     x = x0.clone()
@@ -129,6 +133,8 @@ def main():
     t0 = time.perf_counter()
     stats = []
     for i in range(args.steps):
+        if args.jitter:
+            sc.set_jitter(args.jitter + i)
         st = sc.gn_step(x, **opts)
         stats.append(st)
         print(f"[bench] step {i}: F {st['F_before']:.6g} -> {st['F_after']:.6g} gamma {st['gamma']:.3g} "
@@ -159,7 +165,8 @@ def main():
                                f"{w.spec.env_w}x{w.spec.env_h} at radii {list(w.spec.layer_radii)}, {w.cams.n} cams "
                                f"{w.cams.width}x{w.cams.height} on the upper hemisphere r=4, 40 random spheres/boxes",
                    "rays": sc.n_rays, "params": sc.n_params, "pcg_iters_per_step": args.pcg,
-                   "precond": args.precond, "step_vox": w.spec.step_vox, "aux_lambda": args.aux},
+                   "precond": args.precond, "step_vox": w.spec.step_vox, "aux_lambda": args.aux,
+                   "jitter": args.jitter},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_ray<M_JTJ> (J^T J v)", "avg_launch_ms": jtj_ms,

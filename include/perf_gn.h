@@ -153,6 +153,15 @@ int32_t perf_init_scene(const perf_scene_desc* desc, const perf_camera* cams, in
                         const float* d_targets, void* d_workspace, size_t ws_bytes, void* stream,
                         perf_scene** out);
 int32_t perf_set_targets(perf_scene* s, const float* d_targets);
+/*
+ * Jittering (Sec. IV) for every later call on s: seed != 0 moves each ray's origin to a
+ * pseudo-random point of its pixel and each sample to a pseudo-random point of its own step
+ * (half a step either side of the midpoint for a full step), from the 32-bit finaliser of
+ * MurmurHash3 keyed by (seed, ray, stream); seed 0 = pixel centres and step midpoints.  Keep
+ * one seed for the whole of a perf_gn_step (its residuals, products, preconditioner and
+ * line search must see the same samples) and change it between steps.  Host-side only.
+ */
+int32_t perf_set_jitter(perf_scene* s, uint32_t seed);
 int32_t perf_set_stream(perf_scene* s, void* stream);
 /* Sizes: rays, units (voxels + texels), parameters (4 * units). Any pointer may be NULL. */
 int32_t perf_scene_sizes(const perf_scene* s, int64_t* n_rays, int64_t* n_units, int64_t* n_params);

@@ -94,6 +94,7 @@ SIGNATURES = [
     ("perf_objective", _I32, [_P, _P, _P, ctypes.c_float, _P]),
     ("perf_footprint", _I32, [_P, _P, _P]),
     ("perf_upsample", _I32, [_P, _P, _P, _P, _P]),
+    ("perf_set_jitter", _I32, [_P, ctypes.c_uint32]),
     ("perf_pack_bf16", _I32, [_P, _P, _I64, _P]),
     ("perf_precond_features", _I32, [_P, _P, _P, _P]),
     ("perf_mlp_set_weights", _I32, [_P, _P, _I32]),

@@ -245,6 +245,12 @@ int32_t perf_set_targets(perf_scene* s, const float* d_targets) {
     return PERF_OK;
 }
 
+int32_t perf_set_jitter(perf_scene* s, uint32_t seed) {
+    if (!s) return fail(PERF_EINVAL, "null scene");
+    s->geo.jseed = seed;
+    return PERF_OK;
+}
+
 int32_t perf_set_stream(perf_scene* s, void* stream) {
     if (!s) return fail(PERF_EINVAL, "null scene");
     s->stream = (hipStream_t)stream;

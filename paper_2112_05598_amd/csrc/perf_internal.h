@@ -35,6 +35,7 @@ struct Geo {
     float radius[kMaxLayers];
     float bg[3];
     int nvox;         // voxel units; texel units follow
+    unsigned jseed;   // jittering seed (Sec. IV), 0 = pixel centres and step midpoints
 };
 
 // Device scalars of a Gauss-Newton step (FP64), indices into the scalar array.

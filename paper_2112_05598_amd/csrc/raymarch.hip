@@ -55,12 +55,36 @@ struct Ray {
     float tn, tf, L;
     int K;
     bool hit;
+    unsigned jkey;  // the ray's jittering key (when jittering is on)
     float g0[3], gd[3];
 };
 
-__device__ __forceinline__ void make_ray(const Geo& G, const DevCam& c, int px, int py, Ray& r) {
-    const float dcx = ((float)px + 0.5f - c.cx) / c.fx;
-    const float dcy = ((float)py + 0.5f - c.cy) / c.fy;
+// Jittering (Sec. IV): uniform numbers in [0, 1) from a counter-based generator, the 32-bit
+// finaliser of MurmurHash3 (Appleby), keyed by (seed, ray, stream): streams 0 and 1 are the
+// sub-pixel offsets, stream 2 + k the position of sample k inside its step.  (h >> 8) 2^-24
+// is exact in single precision.
+__device__ __forceinline__ unsigned fmix32(unsigned h) {
+    h ^= h >> 16;
+    h *= 0x85ebca6bu;
+    h ^= h >> 13;
+    h *= 0xc2b2ae35u;
+    h ^= h >> 16;
+    return h;
+}
+__device__ __forceinline__ float jitter_u(unsigned key, unsigned stream) {
+    return (float)(fmix32(key + stream * 0x9e3779b9u) >> 8) * (1.0f / 16777216.0f);
+}
+
+__device__ __forceinline__ void make_ray(const Geo& G, const DevCam& c, int px, int py, long long ray, Ray& r) {
+    float ox = 0.5f, oy = 0.5f;
+    r.jkey = 0u;
+    if (G.jseed) {
+        r.jkey = fmix32(fmix32(G.jseed) ^ (unsigned)ray);
+        ox = jitter_u(r.jkey, 0u);
+        oy = jitter_u(r.jkey, 1u);
+    }
+    const float dcx = ((float)px + ox - c.cx) / c.fx;
+    const float dcy = ((float)py + oy - c.cy) / c.fy;
     float d0 = c.R[0] * dcx + c.R[1] * dcy + c.R[2];
     float d1 = c.R[3] * dcx + c.R[4] * dcy + c.R[5];
     float d2 = c.R[6] * dcx + c.R[7] * dcy + c.R[8];
@@ -105,7 +129,9 @@ __device__ __forceinline__ void make_ray(const Geo& G, const DevCam& c, int px, 
 // Sample k of a ray: step length delta and position in grid coordinates.
 __device__ __forceinline__ float sample_at(const Geo& G, const Ray& r, int k, float g[3]) {
     const float dk = fmaxf(fminf(G.step, r.L - (float)k * G.step), 0.0f);
-    const float s = (float)k * G.step + 0.5f * dk;
+    // the step's midpoint, or with jittering a uniform point of the step itself
+    const float u = G.jseed ? jitter_u(r.jkey, 2u + (unsigned)k) : 0.5f;
+    const float s = (float)k * G.step + u * dk;
     g[0] = r.g0[0] + r.gd[0] * s;
     g[1] = r.g0[1] + r.gd[1] * s;
     g[2] = r.g0[2] + r.gd[2] * s;
@@ -1281,7 +1307,7 @@ __global__ __launch_bounds__(kBlock) void k_ray(Geo G, RayArgs A) {
     XL<PD> X;
     X.p = reinterpret_cast<decltype(X.p)>(A.x);
     Ray r;
-    make_ray(G, A.cams[p.cam], p.px, p.py, r);
+    make_ray(G, A.cams[p.cam], p.px, p.py, p.ray, r);
     if (!p.active) {
         r.K = 0;
         r.hit = false;
@@ -1388,7 +1414,7 @@ __global__ __launch_bounds__(kBlock) void k_footprint(Geo G, const DevCam* cams,
     unsigned long long U = 0, nl = 0, hit = 0;
     if (p.active) {
         Ray r;
-        make_ray(G, cams[p.cam], p.px, p.py, r);
+        make_ray(G, cams[p.cam], p.px, p.py, p.ray, r);
         const int n[3] = {G.nx, G.ny, G.nz};
         int prev_lo[3] = {0, 0, 0}, prev_hi[3] = {-1, -1, -1};
         for (int k = 0; k < r.K; ++k) {

@@ -36,9 +36,11 @@ def level_specs(spec, levels: int) -> List:
 
 
 def gn_hierarchy(spec, cams, targets: torch.Tensor, x0: torch.Tensor, levels: int, steps: Sequence[int],
-                 pcg_iters: int = 30, precond: str = "jacobi", weights=None, F_stop: float = -1.0, log=print):
+                 pcg_iters: int = 30, precond: str = "jacobi", weights=None, F_stop: float = -1.0, log=print,
+                 jitter_base: int = 0):
     """Run the levels; x0 is the coarsest level's start.  Returns the finest x and one record per
-    GN step (level, F before/after, PCG iterations, cumulative wall time in ms)."""
+    GN step (level, F before/after, PCG iterations, cumulative wall time in ms).  jitter_base != 0
+    jitters the samples (Sec. IV) with seed jitter_base + (GN step count) for each step."""
     specs = level_specs(spec, levels)
     if len(steps) != levels:
         raise ValueError("one step count per level")
@@ -53,6 +55,8 @@ def gn_hierarchy(spec, cams, targets: torch.Tensor, x0: torch.Tensor, levels: in
         if precond == "learned":
             sc.mlp_set_weights(weights)
         for _ in range(steps[k]):
+            if jitter_base:
+                sc.set_jitter(jitter_base + len(recs))
             st = sc.gn_step(x, max_iters=pcg_iters, precond=precond)
             torch.cuda.synchronize()
             recs.append({"level": k, "grid": sp.nx, "F_before": st["F_before"], "F_after": st["F_after"],
@@ -76,6 +80,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5, help="GN steps per level")
     ap.add_argument("--pcg", type=int, default=30)
     ap.add_argument("--precond", default="jacobi")
+    ap.add_argument("--jitter", type=int, default=0, help="jitter seed base (0 = off)")
     args = ap.parse_args()
     log = lambda m: print(m, file=sys.stderr, flush=True)  # noqa: E731
     w = ps.workload(args.workload)
@@ -104,7 +109,7 @@ def main():
     specs = level_specs(w.spec, args.levels)
     x0 = torch.from_numpy(ps.init_params(specs[0])).to(dev)
     _, recs = gn_hierarchy(w.spec, w.cams, targets, x0, args.levels, [args.steps] * args.levels, args.pcg,
-                           args.precond, weights, log=log)
+                           args.precond, weights, log=log, jitter_base=args.jitter)
     target = flat[-1]["F_after"]
     hit = next((r for r in recs if r["level"] == args.levels - 1 and r["F_after"] <= target), None)
     print(json.dumps({"workload": args.workload, "levels": [s.nx for s in specs], "steps_per_level": args.steps,

@@ -111,6 +111,11 @@ class Scene:
         if t.dtype != torch.float32 or t.numel() != n or not t.is_contiguous() or t.device != self.device:
             raise ValueError(f"{name} must be a contiguous float32 tensor of {n} elements on {self.device}")
 
+    def set_jitter(self, seed: int):
+        """Jittered ray origins and sample positions (Sec. IV) for every later call; 0 = off.
+        Keep one seed per Gauss-Newton step."""
+        abi.check(self.lib.perf_set_jitter(self.handle, ctypes.c_uint32(int(seed) & 0xFFFFFFFF)))
+
     def set_targets(self, targets: torch.Tensor):
         self._vec(targets, 3 * self.n_rays, "targets")
         self._targets = targets

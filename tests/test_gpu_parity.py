@@ -24,18 +24,19 @@ def rel(a, b):
 
 
 class Case:
-    def __init__(self, name, background=(0.0, 0.0, 0.0), x_kind="init", seed=0, aux=0.0):
+    def __init__(self, name, background=(0.0, 0.0, 0.0), x_kind="init", seed=0, aux=0.0, jitter=0):
         import oracle
         from paper_2112_05598_amd.scene import Scene
-        print(f"[case] {name} x={x_kind} bg={background} aux={aux}", flush=True)
+        print(f"[case] {name} x={x_kind} bg={background} aux={aux} jitter={jitter}", flush=True)
         w = ps.workload(name)
         self.w = w
         self.spec = dataclasses.replace(w.spec, background=background)
-        self.orc = oracle.OracleScene(self.spec, w.cams, aux_lambda=aux)
+        self.orc = oracle.OracleScene(self.spec, w.cams, aux_lambda=aux, jitter_seed=jitter)
         self.targets = self.orc.render(w.x_gt)[0].astype(np.float32)
         self.dev = torch.device("cuda:0")
         self.t_targets = torch.from_numpy(self.targets.reshape(-1)).to(self.dev)
         self.sc = Scene(self.spec, w.cams, self.t_targets, device="cuda:0", aux_lambda=aux)
+        self.sc.set_jitter(jitter)
         if x_kind == "init":
             x = w.x_init.copy()
         elif x_kind == "random":
@@ -55,20 +56,23 @@ class Case:
         self.zero_residual = np.linalg.norm(r) < 1e-3 * np.linalg.norm(H)
 
 
-# (workload, background, parameters, auxiliary-residual weight; the paper's 0.1 where on)
-CASES = [("tiny", (0.0, 0.0, 0.0), "init", 0.0), ("tiny", (0.2, 0.3, 0.1), "random", 0.0),
-         ("small", (0.0, 0.0, 0.0), "random", 0.0), ("ragged", (0.1, 0.1, 0.1), "random", 0.0),
-         ("cfg1", (0.0, 0.0, 0.0), "init", 0.0), ("cfg1", (0.0, 0.0, 0.0), "gt", 0.0),
-         ("ragged", (0.0, 0.0, 0.0), "zero", 0.0),
-         ("small", (0.0, 0.0, 0.0), "random", 0.1), ("ragged", (0.1, 0.1, 0.1), "random", 0.1),
-         ("cfg1", (0.0, 0.0, 0.0), "init", 0.1)]
+# (workload, background, parameters, auxiliary-residual weight (the paper's 0.1 where on),
+#  jitter seed (0 = off))
+CASES = [("tiny", (0.0, 0.0, 0.0), "init", 0.0, 0), ("tiny", (0.2, 0.3, 0.1), "random", 0.0, 0),
+         ("small", (0.0, 0.0, 0.0), "random", 0.0, 0), ("ragged", (0.1, 0.1, 0.1), "random", 0.0, 0),
+         ("cfg1", (0.0, 0.0, 0.0), "init", 0.0, 0), ("cfg1", (0.0, 0.0, 0.0), "gt", 0.0, 0),
+         ("ragged", (0.0, 0.0, 0.0), "zero", 0.0, 0),
+         ("small", (0.0, 0.0, 0.0), "random", 0.1, 0), ("ragged", (0.1, 0.1, 0.1), "random", 0.1, 0),
+         ("cfg1", (0.0, 0.0, 0.0), "init", 0.1, 0),
+         ("small", (0.0, 0.0, 0.0), "random", 0.0, 7), ("ragged", (0.1, 0.1, 0.1), "random", 0.1, 11)]
 
 
 @pytest.fixture(scope="module", params=CASES,
-                ids=lambda c: f"{c[0]}-{c[2]}-bg{c[1][0]}" + (f"-aux{c[3]}" if c[3] else ""))
+                ids=lambda c: f"{c[0]}-{c[2]}-bg{c[1][0]}" + (f"-aux{c[3]}" if c[3] else "")
+                + (f"-jit{c[4]}" if c[4] else ""))
 def case(request):
-    name, bg, kind, aux = request.param
-    return Case(name, bg, kind, aux=aux)
+    name, bg, kind, aux, jit = request.param
+    return Case(name, bg, kind, aux=aux, jitter=jit)
 
 
 def test_render_residuals(case):
