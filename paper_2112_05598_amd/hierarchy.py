@@ -81,6 +81,8 @@ def main():
     ap.add_argument("--pcg", type=int, default=30)
     ap.add_argument("--precond", default="jacobi")
     ap.add_argument("--jitter", type=int, default=0, help="jitter seed base (0 = off)")
+    ap.add_argument("--psnr-views", type=int, default=0,
+                    help="held-out views (seeded, same camera rig) for PSNR of the flat and hierarchical results")
     args = ap.parse_args()
     log = lambda m: print(m, file=sys.stderr, flush=True)  # noqa: E731
     w = ps.workload(args.workload)
@@ -103,18 +105,34 @@ def main():
         torch.cuda.synchronize()
         flat.append({"F_after": st["F_after"], "ms": (time.perf_counter() - t0) * 1e3})
         log(f"[flat] F {st['F_before']:.6g} -> {st['F_after']:.6g}")
+    x_flat = x
     del ref
     torch.cuda.empty_cache()
     # hierarchical: coarse-to-fine from the coarsest level's initial guess
     specs = level_specs(w.spec, args.levels)
     x0 = torch.from_numpy(ps.init_params(specs[0])).to(dev)
-    _, recs = gn_hierarchy(w.spec, w.cams, targets, x0, args.levels, [args.steps] * args.levels, args.pcg,
-                           args.precond, weights, log=log, jitter_base=args.jitter)
+    x_hier, recs = gn_hierarchy(w.spec, w.cams, targets, x0, args.levels, [args.steps] * args.levels, args.pcg,
+                                args.precond, weights, log=log, jitter_base=args.jitter)
+    quality = None
+    if args.psnr_views:
+        from .render import psnr, render_scene
+        held = ps.make_cameras("hemisphere", args.psnr_views, w.cams.width, w.cams.height, 40.0, 4.0,
+                               np.random.default_rng(12345))
+        gt = render_scene(w.spec, held, None, threshold=0.0)
+        images, _ = gt.render_residuals(torch.from_numpy(w.x_gt).to(dev))
+        images = images.clone()
+        del gt
+        quality = {"views": args.psnr_views, "psnr_flat": psnr(x_flat, w.spec, held, images),
+                   "psnr_hierarchy": psnr(x_hier, w.spec, held, images),
+                   "psnr_init": psnr(torch.from_numpy(w.x_init).to(dev), w.spec, held, images)}
+        log(f"[hierarchy] held-out PSNR: init {quality['psnr_init']:.2f} dB, flat {quality['psnr_flat']:.2f} dB, "
+            f"hierarchical {quality['psnr_hierarchy']:.2f} dB")
     target = flat[-1]["F_after"]
     hit = next((r for r in recs if r["level"] == args.levels - 1 and r["F_after"] <= target), None)
     print(json.dumps({"workload": args.workload, "levels": [s.nx for s in specs], "steps_per_level": args.steps,
                       "pcg_iters": args.pcg, "precond": args.precond, "flat": flat, "hierarchy": recs,
-                      "flat_final_F": target, "hierarchy_reaches_flat_F_at_ms": hit["ms"] if hit else None}))
+                      "flat_final_F": target, "hierarchy_reaches_flat_F_at_ms": hit["ms"] if hit else None,
+                      "jitter": args.jitter, "quality": quality}))
 
 
 if __name__ == "__main__":
