@@ -391,6 +391,13 @@ int32_t perf_upsample(const perf_scene_desc* from, const float* d_from, const pe
     return PERF_OK;
 }
 
+int32_t perf_atomic_probe(float* d_y, int64_t n, int32_t reps, void* stream) {
+    if (!d_y && n > 0) return fail(PERF_EINVAL, "null argument");
+    if (n < 0 || reps < 0) return fail(PERF_EINVAL, "negative size");
+    CK(launch_atomic_probe(d_y, n, reps, (hipStream_t)stream));
+    return PERF_OK;
+}
+
 int32_t perf_pack_bf16(const float* d_in, uint16_t* d_out, int64_t n, void* stream) {
     if ((!d_in || !d_out) && n > 0) return fail(PERF_EINVAL, "null argument");
     if (n < 0) return fail(PERF_EINVAL, "negative size");

@@ -10,7 +10,10 @@
 // so the steps add up to the chord L), cell-centred trilinear sampling of (c, sigma),
 // alpha = 1 - exp(-sigma delta) with delta in voxel lengths, exclusive transmittance,
 // then the environment layers (sphere far roots, equirectangular bilinear lookups,
-// opacity used as alpha) and the background.
+// opacity used as alpha) and the background.  With jittering (Sec. IV) the ray starts at
+// a pseudo-random point of its pixel and each sample sits at a pseudo-random point of its
+// step.  The optional auxiliary residual (Sec. III-I, Eq. 10) is a fourth residual per ray
+// that depends on the transmittance through the volume only.
 //
 // Derivatives (Sec. III-E): the forward-mode pass carries the tangent of T and H; the
 // adjoint pass re-marches the ray back to front, as Alg. 1 does, and forms per sample
@@ -144,11 +147,6 @@ struct Corners {
     float f[3];     // fractional position inside the cell
     float w[8];     // weights, corner j = (j&1, j>>1&1, j>>2) offsets
 };
-
-__device__ __forceinline__ float corner_weight(const Corners& c, int j) {
-    return ((j & 1) ? c.f[0] : 1.0f - c.f[0]) * ((j & 2) ? c.f[1] : 1.0f - c.f[1]) *
-           ((j & 4) ? c.f[2] : 1.0f - c.f[2]);
-}
 
 __device__ __forceinline__ void corners(const Geo& G, const float g[3], Corners& c) {
     const int n[3] = {G.nx, G.ny, G.nz};
@@ -512,77 +510,35 @@ struct BrickAtomic {
     }
 };
 
-// Accumulator with NCH = 6 or 9 channels per window voxel, updated like Brick4 by elected
-// read-modify-writes (the feature pass scatters to eight corners per sample, in rotated
-// order).  Channels 0..3 are a float4 plane; the rest a float4 plane and a float plane
-// (NCH = 9) or a float2 plane (NCH = 6).
-template <int NCH>
-struct Brick {
-    static_assert(NCH == 6 || NCH == 9, "6 or 9 channels");
+// The feature pass's accumulator: 6 channels per window voxel (a float4 and a float2 plane),
+// updated like Brick4 by elected read-modify-writes, eight corners per sample in an order
+// rotated by pixel position.
+struct Brick6 {
     Window win;
-    volatile lds_f4* s4;    // [kB3] channels 0..3
-    volatile lds_f4* s4b;   // [kB3] channels 4..7 (NCH = 9)
-    volatile lds_float* s1; // [kB3] channel 8 (NCH = 9)
-    volatile lds_f2* s2;    // [kB3] channels 4..5 (NCH = 6)
-    volatile lds_u8* tag;   // [kB3] lane ids
+    volatile lds_f4* s4;   // [kB3] channels 0..3
+    volatile lds_f2* s2;   // [kB3] channels 4..5
+    volatile lds_u8* tag;  // [kB3] lane ids
 
     __device__ __forceinline__ void init(f4* base, unsigned char* tb) {
         s4 = (volatile lds_f4*)base;
-        if constexpr (NCH == 9) {
-            s4b = (volatile lds_f4*)(base + kB3);
-            s1 = (volatile lds_float*)(base + 2 * kB3);
-        } else {
-            s2 = (volatile lds_f2*)(base + kB3);
-        }
+        s2 = (volatile lds_f2*)(base + kB3);
         tag = (volatile lds_u8*)tb;
         win.o[0] = win.o[1] = win.o[2] = -(1 << 24);
         float* f = (float*)base;
-        for (int i = lane_id(); i < NCH * kB3; i += 64) ((volatile lds_float*)f)[i] = 0.0f;
+        for (int i = lane_id(); i < 6 * kB3; i += 64) ((volatile lds_float*)f)[i] = 0.0f;
     }
     __device__ __forceinline__ bool inside(const int lo[3], const int hi[3]) const { return win.inside(lo, hi); }
-    __device__ __forceinline__ void rmw(int sl, const float v[NCH]) {
-        s4[sl] = s4[sl] + f4{v[0], v[1], v[2], v[3]};
-        if constexpr (NCH == 9) {
-            s4b[sl] = s4b[sl] + f4{v[4], v[5], v[6], v[7]};
-            s1[sl] = s1[sl] + v[8];
-        } else {
-            s2[sl] = s2[sl] + f2{v[4], v[5]};
-        }
-    }
-    // add v to voxel (x, y, z) for every active lane that calls (each lane one voxel)
-    __device__ __forceinline__ void add(int x, int y, int z, const float v[NCH]) {
-        const int sl = ring_slot(x, y, z);
-        const unsigned char lane = (unsigned char)lane_id();
-        bool pend = true;
-        while (wave_any(pend)) {
-            if (pend) tag[sl] = lane;
-            if (pend && tag[sl] == lane) {
-                rmw(sl, v);
-                pend = false;
-            }
-        }
-    }
     template <class F>
     __device__ __forceinline__ void flush_voxel(const Geo& G, int x, int y, int z, F& out) {
         const int sl = ring_slot(x, y, z);
-        float v[NCH];
         const f4 a = s4[sl];
+        const f2 b = s2[sl];
         s4[sl] = f4{0.0f, 0.0f, 0.0f, 0.0f};
-        v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
-        if constexpr (NCH == 9) {
-            const f4 b = s4b[sl];
-            s4b[sl] = f4{0.0f, 0.0f, 0.0f, 0.0f};
-            v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
-            v[8] = s1[sl];
-            s1[sl] = 0.0f;
-        } else {
-            const f2 b = s2[sl];
-            s2[sl] = f2{0.0f, 0.0f};
-            v[4] = b.x; v[5] = b.y;
-        }
+        s2[sl] = f2{0.0f, 0.0f};
+        const float v[6] = {a.x, a.y, a.z, a.w, b.x, b.y};
         bool nz = false;
 #pragma unroll
-        for (int c = 0; c < NCH; ++c) nz |= v[c] != 0.0f;
+        for (int c = 0; c < 6; ++c) nz |= v[c] != 0.0f;
         if (nz && x >= 0 && y >= 0 && z >= 0 && x < G.nx && y < G.ny && z < G.nz) out((z * G.ny + y) * G.nx + x, v);
     }
     template <class F>
@@ -595,19 +551,18 @@ struct Brick {
         auto fl = [&](int x, int y, int z) { flush_voxel(G, x, y, z, out); };
         win.fit(on, lo, hi, fl);
     }
-    // add w_i * base to the 8 corners of every lane that is on (uniform call; NCH = 6), the
-    // corners visited in an order rotated by pixel position as in Brick4
+    // add w_i * base to the 8 corners of every lane that is on (uniform call)
     template <class Sink>
-    __device__ __forceinline__ void scatter8(const Geo& G, bool on, bool inb, const Corners& c, const float base[NCH],
+    __device__ __forceinline__ void scatter8(const Geo& G, bool on, bool inb, const Corners& c, const float base[6],
                                              Sink& out) {
         if (wave_any(on && !inb)) {
             if (on && !inb) {
 #pragma unroll
                 for (int i = 0; i < 8; ++i) {
                     const int x = c.i[0] + (i & 1), y = c.i[1] + ((i >> 1) & 1), z = c.i[2] + (i >> 2);
-                    float vv[NCH];
+                    float vv[6];
 #pragma unroll
-                    for (int q = 0; q < NCH; ++q) vv[q] = base[q] * c.w[i];
+                    for (int q = 0; q < 6; ++q) vv[q] = base[q] * c.w[i];
                     out((z * G.ny + y) * G.nx + x, vv);
                 }
             }
@@ -626,14 +581,14 @@ struct Brick {
             const bool bx = i & 1, by = i & 2, bz = i & 4;
             const int sl = (bz ? sz1 : sz0) + (by ? sy1 : sy0) + (bx ? sx1 : sx0);
             const float w = (bx ? c.f[0] : wx0) * (by ? c.f[1] : wy0) * (bz ? c.f[2] : wz0);
-            float v[NCH];
-#pragma unroll
-            for (int q = 0; q < NCH; ++q) v[q] = base[q] * w;
+            const f4 a = f4{base[0], base[1], base[2], base[3]} * w;
+            const f2 b = f2{base[4], base[5]} * w;
             bool pend = mine;
             while (wave_any(pend)) {
                 if (pend) tag[sl] = lane;
                 if (pend && tag[sl] == lane) {
-                    rmw(sl, v);
+                    s4[sl] = s4[sl] + a;
+                    s2[sl] = s2[sl] + b;
                     pend = false;
                 }
             }
@@ -1185,7 +1140,7 @@ __device__ __forceinline__ void grad_scatter(const Geo& G, const Ray& r, bool li
 // behind the sample (attenuated); for a texel, T_l and T_l S (S behind the layer).
 template <int PD>
 __device__ __forceinline__ void feature_scatter(const Geo& G, const Ray& r, bool live, XL<PD> X, Depth depth,
-                                                Brick<6>& B, TexTable<6>& TT, float* __restrict__ sums) {
+                                                Brick6& B, TexTable<6>& TT, float* __restrict__ sums) {
     SinkFeat sink{sums};
     const float Tx = exp_neg(depth.value());
     float S[3] = {0.0f, 0.0f, 0.0f};
@@ -1394,7 +1349,7 @@ __global__ __launch_bounds__(kBlock) void k_ray(Geo G, RayArgs A) {
             const float g4 = -dr4 * Texit;
             grad_scatter<PD>(G, r, p.active, X, res, p.active ? r4 : 0.0f, g4, depth, B, TT, A.y, A.blocks);
         } else {
-            Brick<NCH> B;
+            Brick6 B;
             B.init(s_brick + wave * NCH * kB3 / 4, s_tag + wave * kB3);
             feature_scatter<PD>(G, r, p.active, X, depth, B, TT, A.y);
         }

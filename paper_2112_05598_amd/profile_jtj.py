@@ -1,17 +1,24 @@
 """Profiling driver for the J^T J v kernel and its HBM-traffic summary.
 
-  run:        python -m paper_2112_05598_amd.profile_jtj run --workload cfg2 --launches 3 --copy-mib 2048
-  summarise:  python -m paper_2112_05598_amd.profile_jtj summarise --fetch F.db --write W.db --out traffic.json
+  run:        python -m paper_2112_05598_amd.profile_jtj run --workload cfg2 --launches 3 --copy-mib 2048 \
+                  [--timing-json T.json]
+  summarise:  python -m paper_2112_05598_amd.profile_jtj summarise --fetch F.db --write W.db --out traffic.json \
+                  [--atomic A.db --timing-json T.json]
 
 `run` launches the library's J^T J v product `--launches` times on the named workload (at the
 initial parameters, with a seeded random v), then one plain device-to-device copy of
 `--copy-mib` MiB (an elementwise b = a * 1) as the calibration kernel.  Run it under `rocprofv3 --pmc FETCH_SIZE` and,
 separately, under `rocprofv3 --pmc WRITE_SIZE`.
 
+`run` ends with the library's atomic probe (one global float atomic add to each of 32 M
+distinct addresses, 4 passes) and, with --timing-json, records the J^T J v kernel's and the
+probe's durations (HIP events on the launch stream) for an unprofiled run.
+
 `summarise` reads the two rocprofv3 result databases, averages each counter per dispatch of the
 J^T J v kernel, scales it by (known copy bytes / counted copy bytes) of the calibration copy,
 and writes the HBM bytes per dispatch together with the sha256 of the kernel source they
-were measured on.
+were measured on.  With --atomic (a TCC_ATOMIC pass) and --timing-json it adds the L2 atomic
+requests per second of the J^T J v kernel against those of the probe.
 """
 from __future__ import annotations
 
@@ -47,6 +54,12 @@ def run(args):
         sc.apply_JtJ(x, v)
         torch.cuda.synchronize()
         print(f"[profile] J^T J v launch {i + 1}/{args.launches} done", flush=True)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    ev[0].record()
+    sc.apply_JtJ(x, v)
+    ev[1].record()
+    torch.cuda.synchronize()
+    jtj_ms = ev[0].elapsed_time(ev[1])
     n = args.copy_mib * (1 << 20) // 4
     a = torch.ones(n, dtype=torch.float32, device=dev)
     b = torch.empty_like(a)
@@ -54,6 +67,25 @@ def run(args):
     torch.mul(a, 1.0, out=b)
     torch.cuda.synchronize()
     print(f"[profile] calibration copy of {args.copy_mib} MiB done", flush=True)
+    import ctypes
+    from paper_2112_05598_amd import abi
+    lib = abi.load()
+    n_probe, reps = 32 << 20, 4
+    y = torch.zeros(n_probe, dtype=torch.float32, device=dev)
+    st = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+    abi.check(lib.perf_atomic_probe(ctypes.c_void_p(y.data_ptr()), n_probe, 1, st))  # warm
+    torch.cuda.synchronize()
+    ev[2].record()
+    abi.check(lib.perf_atomic_probe(ctypes.c_void_p(y.data_ptr()), n_probe, reps, st))
+    ev[3].record()
+    torch.cuda.synchronize()
+    probe_ms = ev[2].elapsed_time(ev[3])
+    assert float(y[0]) == reps + 1 and float(y[-1]) == reps + 1
+    print(f"[profile] atomic probe: {n_probe * reps} atomics in {probe_ms:.2f} ms "
+          f"({n_probe * reps / probe_ms / 1e6:.2f} G atomics/s); J^T J v {jtj_ms:.2f} ms", flush=True)
+    if args.timing_json:
+        with open(args.timing_json, "w") as f:
+            json.dump({"jtj_ms": jtj_ms, "probe_ms": probe_ms, "probe_atomics": n_probe * reps}, f)
 
 
 def _per_dispatch(db: str, counter: str):
@@ -97,6 +129,21 @@ def summarise(args):
         total += b
         out["kernel"] = jname
     out["bytes_per_dispatch"] = total
+    if args.atomic and args.timing_json:
+        tm = json.load(open(args.timing_json))
+        per = _per_dispatch(args.atomic, "TCC_ATOMIC")
+        jtj = [(n, v) for n, v in per.items() if JTJ_TAG in n]
+        probe = [(n, v) for n, v in per.items() if "k_atomic_probe" in n]
+        if len(jtj) != 1 or not probe:
+            raise SystemExit(f"{args.atomic}: expected the J^T J v kernel and the probe, found {list(per)}")
+        (_, (ja, _)), = jtj
+        pa = max(v[0] for _, v in probe)  # the 4-pass dispatch (the warm-up makes 1 pass)
+        out["atomics"] = {"jtj_requests_per_dispatch": ja, "jtj_ms": tm["jtj_ms"],
+                          "jtj_requests_per_s": ja / (tm["jtj_ms"] * 1e-3),
+                          "probe_requests_per_dispatch": pa, "probe_ms": tm["probe_ms"],
+                          "probe_requests_per_s": pa / (tm["probe_ms"] * 1e-3),
+                          "probe_atomics": tm["probe_atomics"]}
+        out["atomics"]["frac_of_probe"] = out["atomics"]["jtj_requests_per_s"] / out["atomics"]["probe_requests_per_s"]
     with open(args.out, "w") as f:
         json.dump(out, f, indent=1)
     print(json.dumps(out, indent=1))
@@ -109,12 +156,15 @@ def main():
     r.add_argument("--workload", default="cfg2")
     r.add_argument("--launches", type=int, default=3)
     r.add_argument("--copy-mib", type=int, default=2048)
+    r.add_argument("--timing-json", default="")
     s = sub.add_parser("summarise")
     s.add_argument("--fetch", required=True)
     s.add_argument("--write", required=True)
     s.add_argument("--workload", default="cfg2")
     s.add_argument("--copy-mib", type=int, default=2048)
     s.add_argument("--out", required=True)
+    s.add_argument("--atomic", default="")
+    s.add_argument("--timing-json", default="")
     args = ap.parse_args()
     run(args) if args.cmd == "run" else summarise(args)
 

@@ -1,0 +1,17 @@
+"""The atomic-throughput probe used by the profiling driver adds exactly reps to every element."""
+import pytest
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def test_atomic_probe_counts():
+    import ctypes
+    from paper_2112_05598_amd import abi
+    lib = abi.load()
+    n = (1 << 20) + 37  # a ragged tail past the last full workgroup
+    y = torch.zeros(n, dtype=torch.float32, device="cuda:0")
+    st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    abi.check(lib.perf_atomic_probe(ctypes.c_void_p(y.data_ptr()), n, 3, st))
+    torch.cuda.synchronize()
+    assert torch.all(y == 3.0)
