@@ -245,11 +245,12 @@ int32_t perf_upsample(const perf_scene_desc* from, const float* d_from, const pe
 
 /*
  * Measurement probe (not part of the method): reps passes of one global float atomic add of
- * 1.0 (no return value) to each of d_y[0..n), distinct consecutive addresses, the pattern of
- * the J^T scatter's window flushes.  Profiling divides the atomic requests the J^T J v kernel
- * issues per second by the rate this probe reaches.  d_y is caller-owned; asynchronous on stream.
+ * 1.0 (no return value) to each of d_y[i * stride], i < n (distinct addresses; stride 1 =
+ * consecutive, many lanes per L2 request; stride 32 = one 128-byte line per lane, like the
+ * J^T scatter's scattered window flushes).  Profiling compares the atomic requests per second
+ * of the J^T J v kernel with this probe's.  d_y [n * stride] is caller-owned; asynchronous.
  */
-int32_t perf_atomic_probe(float* d_y, int64_t n, int32_t reps, void* stream);
+int32_t perf_atomic_probe(float* d_y, int64_t n, int32_t reps, int32_t stride, void* stream);
 
 /* Round FP32 parameters to bfloat16 storage (round to nearest even): d_out[n] uint16. */
 int32_t perf_pack_bf16(const float* d_in, uint16_t* d_out, int64_t n, void* stream);

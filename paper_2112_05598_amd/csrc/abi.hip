@@ -391,10 +391,11 @@ int32_t perf_upsample(const perf_scene_desc* from, const float* d_from, const pe
     return PERF_OK;
 }
 
-int32_t perf_atomic_probe(float* d_y, int64_t n, int32_t reps, void* stream) {
+int32_t perf_atomic_probe(float* d_y, int64_t n, int32_t reps, int32_t stride, void* stream) {
     if (!d_y && n > 0) return fail(PERF_EINVAL, "null argument");
-    if (n < 0 || reps < 0) return fail(PERF_EINVAL, "negative size");
-    CK(launch_atomic_probe(d_y, n, reps, (hipStream_t)stream));
+    if (n < 0 || reps < 0 || stride < 1) return fail(PERF_EINVAL, "need n, reps >= 0 and stride >= 1");
+    if (n > 0 && (n - 1) > (int64_t)1 << 40) return fail(PERF_EUNSUPPORTED, "probe too large");
+    CK(launch_atomic_probe(d_y, n, reps, stride, (hipStream_t)stream));
     return PERF_OK;
 }
 

@@ -356,12 +356,15 @@ unsigned grid_for(int64_t n) {
 }
 
 // Measurement probe: reps passes of one global float atomic add (no return) to each of n
-// distinct consecutive addresses, the access pattern of the J^T scatter's window flushes;
-// used to calibrate the atomic throughput the scatter is compared against.
-__global__ __launch_bounds__(kVecBlock) void k_atomic_probe(float* __restrict__ y, int64_t n, int reps) {
+// distinct addresses `stride` floats apart (1: consecutive, many lanes per L2 request; 32:
+// one 128-byte line per lane, one lane per request, like the scattered flushes of the J^T
+// scatter's window slabs); used to calibrate the atomic throughput the scatter is compared
+// against.
+__global__ __launch_bounds__(kVecBlock) void k_atomic_probe(float* __restrict__ y, int64_t n, int reps,
+                                                           int stride) {
     for (int r = 0; r < reps; ++r)
         for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-            unsafeAtomicAdd(y + i, 1.0f);
+            unsafeAtomicAdd(y + i * stride, 1.0f);
 }
 
 }  // namespace
@@ -465,9 +468,9 @@ hipError_t launch_trial(const float* x, const float* delta, float gamma, int64_t
     return hipGetLastError();
 }
 
-hipError_t launch_atomic_probe(float* y, int64_t n, int reps, hipStream_t st) {
+hipError_t launch_atomic_probe(float* y, int64_t n, int reps, int stride, hipStream_t st) {
     if (n <= 0 || reps <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_atomic_probe, dim3(grid_for(n)), dim3(kVecBlock), 0, st, y, n, reps);
+    hipLaunchKernelGGL(k_atomic_probe, dim3(grid_for(n)), dim3(kVecBlock), 0, st, y, n, reps, stride);
     return hipGetLastError();
 }
 

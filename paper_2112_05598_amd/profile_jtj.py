@@ -70,22 +70,28 @@ def run(args):
     import ctypes
     from paper_2112_05598_amd import abi
     lib = abi.load()
-    n_probe, reps = 32 << 20, 4
-    y = torch.zeros(n_probe, dtype=torch.float32, device=dev)
     st = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
-    abi.check(lib.perf_atomic_probe(ctypes.c_void_p(y.data_ptr()), n_probe, 1, st))  # warm
-    torch.cuda.synchronize()
-    ev[2].record()
-    abi.check(lib.perf_atomic_probe(ctypes.c_void_p(y.data_ptr()), n_probe, reps, st))
-    ev[3].record()
-    torch.cuda.synchronize()
-    probe_ms = ev[2].elapsed_time(ev[3])
-    assert float(y[0]) == reps + 1 and float(y[-1]) == reps + 1
-    print(f"[profile] atomic probe: {n_probe * reps} atomics in {probe_ms:.2f} ms "
-          f"({n_probe * reps / probe_ms / 1e6:.2f} G atomics/s); J^T J v {jtj_ms:.2f} ms", flush=True)
+    timing = {"jtj_ms": jtj_ms}
+    # consecutive addresses (stride 1), then one 128-byte line per lane (stride 32); the
+    # scattered probe dispatches reps = 2 so the two are told apart in the counter database
+    for stride, n_probe, reps in ((1, 32 << 20, 4), (32, 8 << 20, 2)):
+        y = torch.zeros(n_probe * stride, dtype=torch.float32, device=dev)
+        abi.check(lib.perf_atomic_probe(ctypes.c_void_p(y.data_ptr()), n_probe, 1, stride, st))  # warm
+        torch.cuda.synchronize()
+        ev[2].record()
+        abi.check(lib.perf_atomic_probe(ctypes.c_void_p(y.data_ptr()), n_probe, reps, stride, st))
+        ev[3].record()
+        torch.cuda.synchronize()
+        ms = ev[2].elapsed_time(ev[3])
+        assert float(y[0]) == reps + 1 and float(y[(n_probe - 1) * stride]) == reps + 1
+        print(f"[profile] atomic probe, stride {stride}: {n_probe * reps} atomics in {ms:.3f} ms "
+              f"({n_probe * reps / ms / 1e6:.2f} G atomics/s); J^T J v {jtj_ms:.2f} ms", flush=True)
+        timing[f"probe{stride}_ms"] = ms
+        timing[f"probe{stride}_atomics"] = n_probe * reps
+        del y
     if args.timing_json:
         with open(args.timing_json, "w") as f:
-            json.dump({"jtj_ms": jtj_ms, "probe_ms": probe_ms, "probe_atomics": n_probe * reps}, f)
+            json.dump(timing, f)
 
 
 def _per_dispatch(db: str, counter: str):
@@ -137,13 +143,28 @@ def summarise(args):
         if len(jtj) != 1 or not probe:
             raise SystemExit(f"{args.atomic}: expected the J^T J v kernel and the probe, found {list(per)}")
         (_, (ja, _)), = jtj
-        pa = max(v[0] for _, v in probe)  # the 4-pass dispatch (the warm-up makes 1 pass)
         out["atomics"] = {"jtj_requests_per_dispatch": ja, "jtj_ms": tm["jtj_ms"],
-                          "jtj_requests_per_s": ja / (tm["jtj_ms"] * 1e-3),
-                          "probe_requests_per_dispatch": pa, "probe_ms": tm["probe_ms"],
-                          "probe_requests_per_s": pa / (tm["probe_ms"] * 1e-3),
-                          "probe_atomics": tm["probe_atomics"]}
-        out["atomics"]["frac_of_probe"] = out["atomics"]["jtj_requests_per_s"] / out["atomics"]["probe_requests_per_s"]
+                          "jtj_requests_per_s": ja / (tm["jtj_ms"] * 1e-3)}
+        # per-dispatch request counts of the probe dispatches in launch order: warm-up and timed
+        # pass of stride 1, then of stride 32 (_per_dispatch averages per kernel name, so read
+        # the dispatches here one by one)
+        con = sqlite3.connect(args.atomic)
+        tab = next(r[0] for r in con.execute("select name from sqlite_master where type in ('table', 'view')")
+                   if r[0].startswith("counters_collection"))
+        cols = [r[1] for r in con.execute(f"pragma table_info('{tab}')")]
+        did = next(c for c in ("dispatch_id", "correlation_id", "id") if c in cols)
+        rows = con.execute(f"select {did}, sum(value) from '{tab}' where kernel_name like '%k_atomic_probe%' "
+                           f"and counter_name = 'TCC_ATOMIC' group by {did} order by {did}").fetchall()
+        if len(rows) != 4:
+            raise SystemExit(f"{args.atomic}: expected 4 probe dispatches, found {len(rows)}")
+        for (stride, idx) in ((1, 1), (32, 3)):
+            req = float(rows[idx][1])
+            ms = tm[f"probe{stride}_ms"]
+            out["atomics"][f"probe{stride}"] = {"requests_per_dispatch": req, "ms": ms,
+                                                "requests_per_s": req / (ms * 1e-3),
+                                                "lanes_per_request": tm[f"probe{stride}_atomics"] / req}
+        out["atomics"]["frac_of_scattered_probe"] = (out["atomics"]["jtj_requests_per_s"]
+                                                     / out["atomics"]["probe32"]["requests_per_s"])
     with open(args.out, "w") as f:
         json.dump(out, f, indent=1)
     print(json.dumps(out, indent=1))
