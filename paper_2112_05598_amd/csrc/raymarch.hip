@@ -237,9 +237,10 @@ __device__ __forceinline__ float one_minus_exp_neg(float t, float e) {
 }
 
 // ------------------------------------------------------------------ lane swaps (DPP)
-// Value of lane ^ 1 (quad permutation 1,0,3,2) and of lane ^ 8 (rotation by 8 inside each
-// row of 16 lanes).  Called with every lane of the wave active.
+// Value of lane ^ 1 (quad permutation 1,0,3,2), of lane ^ 2 (quad permutation 2,3,0,1) and of
+// lane ^ 8 (rotation by 8 inside each row of 16 lanes).  Called with every lane of the wave active.
 __device__ __forceinline__ int dpp_xor1(int v) { return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false); }
+__device__ __forceinline__ int dpp_xor2(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false); }
 __device__ __forceinline__ int dpp_row_xor8(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x128, 0xF, 0xF, false); }
 __device__ __forceinline__ float dpp_xor1(float v) { return __int_as_float(dpp_xor1(__float_as_int(v))); }
 __device__ __forceinline__ float dpp_row_xor8(float v) { return __int_as_float(dpp_row_xor8(__float_as_int(v))); }
@@ -569,8 +570,17 @@ struct Brick6 {
         }
         const bool mine = on && inb;
         if (!wave_any(mine)) return;
-        const unsigned char lane = (unsigned char)lane_id();
-        const int phi = ((lane & 7) + 3 * (lane >> 3)) & 7;
+        const int lid = lane_id();
+        const unsigned char lane = (unsigned char)lid;
+        // fold the x and y neighbours' corners into this lane when they share its cell, as the
+        // J^T scatter does (same swaps, same corner order for the lanes of a 2x2 quad)
+        const int key = mine ? c.v : -1;
+        const bool gx = mine & (dpp_xor1(key) == key);
+        const bool keep_x = mine & !(gx & ((lid & 1) != 0));
+        const int key2 = keep_x ? key : -1;
+        const bool gy = keep_x & (dpp_row_xor8(key2) == key2);
+        const bool keep = keep_x & !(gy & (((lid >> 3) & 1) != 0));
+        const int phi = (((lid & 7) >> 1) + 3 * (lid >> 4)) & 7;
         const int sx0 = c.i[0] & 7, sx1 = (c.i[0] + 1) & 7;
         const int sy0 = (c.i[1] & 7) << 3, sy1 = ((c.i[1] + 1) & 7) << 3;
         const int sz0 = (c.i[2] & 7) << 6, sz1 = ((c.i[2] + 1) & 7) << 6;
@@ -580,10 +590,22 @@ struct Brick6 {
             const int i = (r + phi) & 7;
             const bool bx = i & 1, by = i & 2, bz = i & 4;
             const int sl = (bz ? sz1 : sz0) + (by ? sy1 : sy0) + (bx ? sx1 : sx0);
-            const float w = (bx ? c.f[0] : wx0) * (by ? c.f[1] : wy0) * (bz ? c.f[2] : wz0);
-            const f4 a = f4{base[0], base[1], base[2], base[3]} * w;
-            const f2 b = f2{base[4], base[5]} * w;
-            bool pend = mine;
+            const float w = mine ? (bx ? c.f[0] : wx0) * (by ? c.f[1] : wy0) * (bz ? c.f[2] : wz0) : 0.0f;
+            f4 a = f4{base[0], base[1], base[2], base[3]} * w;
+            f2 b = f2{base[4], base[5]} * w;
+            const f4 ax = dpp_xor1(a);
+            const f2 bxx = f2{dpp_xor1(b.x), dpp_xor1(b.y)};
+            if (gx) {
+                a += ax;
+                b += bxx;
+            }
+            const f4 ay = dpp_row_xor8(a);
+            const f2 by8 = f2{dpp_row_xor8(b.x), dpp_row_xor8(b.y)};
+            if (gy) {
+                a += ay;
+                b += by8;
+            }
+            bool pend = keep;
             while (wave_any(pend)) {
                 if (pend) tag[sl] = lane;
                 if (pend && tag[sl] == lane) {
@@ -974,15 +996,35 @@ __device__ __forceinline__ void grad_flush_slot(const Geo& G, unsigned pend, con
                                                 float r4, float g4, BrickAtomic<9>& B, const SinkGrad& sink) {
     const bool mine = (pend >> SLOT) & 1u;
     if (!wave_any(mine)) return;
-    if (!mine) return;
     const int x = w.i[0] + (((SLOT >> 0) ^ w.i[0]) & 1);
     const int y = w.i[1] + (((SLOT >> 1) ^ w.i[1]) & 1);
     const int z = w.i[2] + (((SLOT >> 2) ^ w.i[2]) & 1);
     const float a = w.a[SLOT], s0 = w.s0[SLOT], s1 = w.s1[SLOT], s2 = w.s2[SLOT];
     const float q = g4 * w.s3[SLOT];  // the auxiliary residual's sigma partial (0 when off)
-    const float v[9] = {-a * rr[0], -a * rr[1], -a * rr[2], -(s0 * rr[0] + s1 * rr[1] + s2 * rr[2] + q * r4),
-                        a * a,      a * s0,     a * s1,     a * s2,
-                        s0 * s0 + s1 * s1 + s2 * s2 + q * q};
+    float v[9] = {-a * rr[0], -a * rr[1], -a * rr[2], -(s0 * rr[0] + s1 * rr[1] + s2 * rr[2] + q * r4),
+                  a * a,      a * s0,     a * s1,     a * s2,
+                  s0 * s0 + s1 * s1 + s2 * s2 + q * q};
+    // Neighbouring rays hand over the same voxel at the same step, and their LDS atomics on one
+    // address serialise.  Fold the x neighbour's (lane ^ 1), the y neighbour's (lane ^ 8) and
+    // then lane ^ 2's product into this lane when the voxel is the same; the donor drops out.
+    // Straight-line code with every lane active (the swaps read the partner's registers).
+    const int lane = lane_id();
+    const int key = mine ? (z * G.ny + y) * G.nx + x : -1;
+    bool keep = mine;
+    auto fold = [&](auto swap, int bit) {
+        const int kc = keep ? key : -1;
+        const bool g = keep & (swap(kc) == kc);
+#pragma unroll
+        for (int c = 0; c < 9; ++c) {
+            const float t = __int_as_float(swap(__float_as_int(v[c])));
+            v[c] = g ? v[c] + t : v[c];
+        }
+        keep = keep & !(g & ((lane & bit) != 0));
+    };
+    fold([](int u) { return dpp_xor1(u); }, 1);
+    fold([](int u) { return dpp_row_xor8(u); }, 8);
+    fold([](int u) { return dpp_xor2(u); }, 2);
+    if (!keep) return;
     const int lo[3] = {x, y, z};
     if (B.inside(lo, lo)) B.add(x, y, z, v);
     else sink((z * G.ny + y) * G.nx + x, v);
@@ -1167,7 +1209,7 @@ __device__ __forceinline__ void feature_scatter(const Geo& G, const Ray& r, bool
         const int m = j - off;
         const bool on = m >= 0 && m < r.K;
         const int k = r.K - 1 - m;
-        Corners c;
+        Corners c{};
         float dk = 0.0f;
         int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
         if (on) {
@@ -1181,16 +1223,25 @@ __device__ __forceinline__ void feature_scatter(const Geo& G, const Ray& r, bool
             }
         }
         B.fit(G, on, lo, hi, sink);
-        if (!on) continue;
-        float sg, c0, c1, c2;
-        gather<PD>(X, c, nx, nxy, sg, c0, c1, c2);
-        const float tau = sg * dk;
-        depth.add(-tau);
-        const float T = (k == 0) ? 1.0f : exp_neg(depth.value());
-        const float al = one_minus_exp_neg(tau, exp_neg(tau));
-        const float A = T * al;
-        const float base6[6] = {1.0f, T, G0, G1, G2, al};
-        B.scatter8(G, true, B.inside(lo, hi), c, base6, sink);
+        float base6[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+        float A = 0.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
+        if (on) {
+            float sg;
+            gather<PD>(X, c, nx, nxy, sg, c0, c1, c2);
+            const float tau = sg * dk;
+            depth.add(-tau);
+            const float T = (k == 0) ? 1.0f : exp_neg(depth.value());
+            const float al = one_minus_exp_neg(tau, exp_neg(tau));
+            A = T * al;
+            base6[0] = 1.0f;
+            base6[1] = T;
+            base6[2] = G0;
+            base6[3] = G1;
+            base6[4] = G2;
+            base6[5] = al;
+        }
+        // every lane takes part (the scatter swaps registers between lanes)
+        B.scatter8(G, on, on && B.inside(lo, hi), c, base6, sink);
         G0 += A * c0;
         G1 += A * c1;
         G2 += A * c2;
