@@ -12,7 +12,8 @@ parameters; the solve starts from grey colour 0.5, opacity 0.01.
 value = rays pushed through J^T J v per second of whole-step wall time (every other
 part of the step counts as overhead).  The roofline object prices the J^T J v kernel
 alone: footprint bytes per launch (48 B per distinct voxel a ray touches + 192 B per
-environment layer it hits, counted exactly by the library's footprint pass) over the
+environment layer it hits, 40 B and 160 B with bf16 parameter storage, counted exactly by
+the library's footprint pass) over the
 kernel's average duration measured with HIP events on the launch stream.
 """
 from __future__ import annotations
@@ -118,7 +119,9 @@ def main():
                    aux_lambda=args.aux)
     _, tot = sc.footprint(per_ray=False)
     tot = tot.cpu().numpy()
-    bytes_per_launch = 48.0 * float(tot[0]) + 192.0 * float(tot[1])
+    # per distinct voxel: x (16 B, or 8 B stored as bf16) + v (16 B) + y (16 B); per layer hit: 4 texels
+    per_unit = 48.0 if args.dtype == "f32" else 40.0
+    bytes_per_launch = per_unit * float(tot[0]) + 4.0 * per_unit * float(tot[1])
 
     x0 = torch.from_numpy(w.x_init).to(dev)
     opts = dict(max_iters=args.pcg, precond=args.precond)
