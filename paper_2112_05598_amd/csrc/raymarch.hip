@@ -239,9 +239,9 @@ __device__ __forceinline__ float one_minus_exp_neg(float t, float e) {
 // ------------------------------------------------------------------ lane swaps (DPP)
 // Value of lane ^ 1 (quad permutation 1,0,3,2), of lane ^ 2 (quad permutation 2,3,0,1) and of
 // lane ^ 8 (rotation by 8 inside each row of 16 lanes).  Called with every lane of the wave active.
-__device__ __forceinline__ int dpp_xor1(int v) { return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false); }
-__device__ __forceinline__ int dpp_xor2(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false); }
-__device__ __forceinline__ int dpp_row_xor8(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x128, 0xF, 0xF, false); }
+__device__ __forceinline__ int dpp_xor1(int v) { return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, true); }
+__device__ __forceinline__ int dpp_xor2(int v) { return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, true); }
+__device__ __forceinline__ int dpp_row_xor8(int v) { return __builtin_amdgcn_mov_dpp(v, 0x128, 0xF, 0xF, true); }
 __device__ __forceinline__ float dpp_xor1(float v) { return __int_as_float(dpp_xor1(__float_as_int(v))); }
 __device__ __forceinline__ float dpp_row_xor8(float v) { return __int_as_float(dpp_row_xor8(__float_as_int(v))); }
 
@@ -395,6 +395,9 @@ struct Brick4 {
             out((z * G.ny + y) * G.nx + x, vv);
         }
     }
+    __device__ __forceinline__ void clear_head(int n) {
+        for (int i = lane_id(); i < n; i += 64) s[i] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+    }
     template <class Sink>
     __device__ __forceinline__ void fit(const Geo& G, bool on, const int lo[3], const int hi[3], Sink& out) {
         auto fl = [&](int x, int y, int z) { flush_voxel(G, x, y, z, out); };
@@ -440,6 +443,8 @@ struct Brick4 {
         const int ky = dpp_row_xor8(key2);
         const bool gy = keep_x & (ky == key2);                     // y neighbour (after x) too
         const bool keep = keep_x & !(gy & (((lane >> 3) & 1) != 0));
+        const bool give_x = gx & ((lane & 1) != 0);
+        const bool give_y = gy & (((lane >> 3) & 1) != 0);
         const int phi = (((lane & 7) >> 1) + 3 * (lane >> 4)) & 7;
         const int sx0 = c.i[0] & 7, sx1 = (c.i[0] + 1) & 7;
         const int sy0 = (c.i[1] & 7) << 3, sy1 = ((c.i[1] + 1) & 7) << 3;
@@ -451,17 +456,26 @@ struct Brick4 {
             const bool bx = i & 1, by = i & 2, bz = i & 4;
             const int sl = (bz ? sz1 : sz0) + (by ? sy1 : sy0) + (bx ? sx1 : sx0);
             const float w = mine ? (bx ? c.f[0] : wx0) * (by ? c.f[1] : wy0) * (bz ? c.f[2] : wz0) : 0.0f;
-            f4 add = val * w;
-            const f4 ax = dpp_xor1(add);
-            if (gx) add += ax;
-            const f4 ay = dpp_row_xor8(add);
-            if (gy) add += ay;
+            f4 add;
+            {
+#pragma clang fp contract(off)
+                add = val * w;
+                // a donor hands its value over; every other lane hands over zero
+                const f4 zero = f4{0.0f, 0.0f, 0.0f, 0.0f};
+                add += dpp_xor1(give_x ? add : zero);
+                add += dpp_row_xor8(give_y ? add : zero);
+            }
             bool pend = keep;
             while (wave_any(pend)) {
-                if (pend) tag[sl] = tag_id;
-                if (pend && tag[sl] == tag_id) {
-                    s[sl] = s[sl] + add;
-                    pend = false;
+                if (pend) {
+                    tag[sl] = tag_id;
+                    // read the slot with the tag, so a round waits on LDS once
+                    const unsigned char t = tag[sl];
+                    const f4 cur = s[sl];
+                    if (t == tag_id) {
+                        s[sl] = cur + add;
+                        pend = false;
+                    }
                 }
             }
         }
@@ -580,6 +594,8 @@ struct Brick6 {
         const int key2 = keep_x ? key : -1;
         const bool gy = keep_x & (dpp_row_xor8(key2) == key2);
         const bool keep = keep_x & !(gy & (((lid >> 3) & 1) != 0));
+        const bool give_x = gx & ((lid & 1) != 0);
+        const bool give_y = gy & (((lid >> 3) & 1) != 0);
         const int phi = (((lid & 7) >> 1) + 3 * (lid >> 4)) & 7;
         const int sx0 = c.i[0] & 7, sx1 = (c.i[0] + 1) & 7;
         const int sy0 = (c.i[1] & 7) << 3, sy1 = ((c.i[1] + 1) & 7) << 3;
@@ -591,27 +607,35 @@ struct Brick6 {
             const bool bx = i & 1, by = i & 2, bz = i & 4;
             const int sl = (bz ? sz1 : sz0) + (by ? sy1 : sy0) + (bx ? sx1 : sx0);
             const float w = mine ? (bx ? c.f[0] : wx0) * (by ? c.f[1] : wy0) * (bz ? c.f[2] : wz0) : 0.0f;
-            f4 a = f4{base[0], base[1], base[2], base[3]} * w;
-            f2 b = f2{base[4], base[5]} * w;
-            const f4 ax = dpp_xor1(a);
-            const f2 bxx = f2{dpp_xor1(b.x), dpp_xor1(b.y)};
-            if (gx) {
-                a += ax;
-                b += bxx;
-            }
-            const f4 ay = dpp_row_xor8(a);
-            const f2 by8 = f2{dpp_row_xor8(b.x), dpp_row_xor8(b.y)};
-            if (gy) {
-                a += ay;
-                b += by8;
+            f4 a;
+            f2 b;
+            {
+#pragma clang fp contract(off)
+                a = f4{base[0], base[1], base[2], base[3]} * w;
+                b = f2{base[4], base[5]} * w;
+                const f4 z4 = f4{0.0f, 0.0f, 0.0f, 0.0f};
+                const f2 z2 = f2{0.0f, 0.0f};
+                const f4 ga = give_x ? a : z4;
+                const f2 gb = give_x ? b : z2;
+                a += dpp_xor1(ga);
+                b += f2{dpp_xor1(gb.x), dpp_xor1(gb.y)};
+                const f4 ha = give_y ? a : z4;
+                const f2 hb = give_y ? b : z2;
+                a += dpp_row_xor8(ha);
+                b += f2{dpp_row_xor8(hb.x), dpp_row_xor8(hb.y)};
             }
             bool pend = keep;
             while (wave_any(pend)) {
-                if (pend) tag[sl] = lane;
-                if (pend && tag[sl] == lane) {
-                    s4[sl] = s4[sl] + a;
-                    s2[sl] = s2[sl] + b;
-                    pend = false;
+                if (pend) {
+                    tag[sl] = lane;
+                    const unsigned char t = tag[sl];
+                    const f4 c4 = s4[sl];
+                    const f2 c2 = s2[sl];
+                    if (t == lane) {
+                        s4[sl] = c4 + a;
+                        s2[sl] = c2 + b;
+                        pend = false;
+                    }
                 }
             }
         }
@@ -917,6 +941,7 @@ __device__ __forceinline__ void adjoint_scatter(const Geo& G, const Ray& r, bool
         uE = u[0] * S[0] + u[1] * S[1] + u[2] * S[2];
     }
     TT.flush(sink);
+    B.clear_head(16);  // the table's keys (the table's sums are left at zero by the flush)
     float uG = Tx * uE;  // u . G_k
     float Tn = Tx;       // T_{k+1}
     const int nx = G.nx, nxy = G.nx * G.ny;
@@ -1014,12 +1039,10 @@ __device__ __forceinline__ void grad_flush_slot(const Geo& G, unsigned pend, con
     auto fold = [&](auto swap, int bit) {
         const int kc = keep ? key : -1;
         const bool g = keep & (swap(kc) == kc);
+        const bool give = g & ((lane & bit) != 0);
 #pragma unroll
-        for (int c = 0; c < 9; ++c) {
-            const float t = __int_as_float(swap(__float_as_int(v[c])));
-            v[c] = g ? v[c] + t : v[c];
-        }
-        keep = keep & !(g & ((lane & bit) != 0));
+        for (int c = 0; c < 9; ++c) v[c] += __int_as_float(swap(__float_as_int(give ? v[c] : 0.0f)));
+        keep = keep & !give;
     };
     fold([](int u) { return dpp_xor1(u); }, 1);
     fold([](int u) { return dpp_row_xor8(u); }, 8);
@@ -1305,8 +1328,8 @@ __global__ __launch_bounds__(kBlock) void k_ray(Geo G, RayArgs A) {
     __shared__ f4 s_brick[(SCATTER && !JT) ? kWaves * NCH * kB3 / 4 : 1];
     __shared__ f4 s_brick4[JT ? kWaves * kB3 : 1];
     __shared__ unsigned char s_tag[SCATTER ? kWaves * kB3 : 1];
-    __shared__ float s_tab[SCATTER ? kWaves * NCH * 64 : 1];
-    __shared__ int s_keys[SCATTER ? kWaves * 64 : 1];
+    __shared__ float s_tab[(SCATTER && !JT) ? kWaves * NCH * 64 : 1];
+    __shared__ int s_keys[(SCATTER && !JT) ? kWaves * 64 : 1];
     if (A.done && *A.done) return;
     const Pix p = pixel_of(G);
     const int wave = threadIdx.x >> 6;
@@ -1361,10 +1384,12 @@ __global__ __launch_bounds__(kBlock) void k_ray(Geo G, RayArgs A) {
         }
     } else if constexpr (SCATTER) {
         TexTable<NCH> TT;
-        TT.init(s_keys + wave * 64, s_tab + wave * NCH * 64);
+        if constexpr (!JT) TT.init(s_keys + wave * 64, s_tab + wave * NCH * 64);
         if constexpr (JT) {
             Brick4 B;
             B.init(s_brick4 + wave * kB3, s_tag + wave * kB3);
+            // the texel table borrows the head of the window's storage until it is flushed
+            TT.init((int*)(s_brick4 + wave * kB3), (float*)(s_brick4 + wave * kB3 + 16));
             float u[3] = {0.0f, 0.0f, 0.0f};
             float u4 = 0.0f;
             if (p.active) {
