@@ -305,6 +305,14 @@ __device__ __forceinline__ int ring_slot(int x, int y, int z) {
     return ((z & (kB - 1)) * kB + (y & (kB - 1))) * kB + (x & (kB - 1));
 }
 
+// Corner order of the elected scatters.  The 2x2 lane quad to the right of another visits corner
+// k + 2 in the round where that one visits corner k, the quad below it corner k + 1.  Two
+// face-adjacent cells then never update one voxel in the same round, except when the right-hand
+// quad's cell lies at -y or the lower quad's at -x; mirroring the corners' y offset when the
+// camera's right vector points to -y, and their x offset when its down vector points to -x,
+// removes those cases.  This mask holds the mirrored axes.
+__device__ __forceinline__ int corner_mask(const DevCam& c) { return (c.R[1] < 0.0f ? 1 : 0) | (c.R[3] < 0.0f ? 2 : 0); }
+
 // Window bookkeeping shared by the accumulator kinds: origin, fit and slab iteration.
 struct Window {
     int o[3];  // window origin (voxel coordinates), wave-uniform
@@ -375,6 +383,7 @@ struct Window {
 // mostly target different voxels in the same round.
 struct Brick4 {
     Window win;
+    int cmask;            // corner-order mirror of the camera (corner_mask)
     volatile lds_f4* s;   // [kB3]
     volatile lds_u8* tag; // [kB3] lane ids
 
@@ -414,7 +423,8 @@ struct Brick4 {
     // when they sit in the same cell, through DPP lane swaps, so one lane per combined group
     // enters the election.  Lanes of different cells never target one voxel with the same
     // corner index, so every lane of a 2x2 lane quad visits the corners in the same order,
-    // rotated per quad to spread same-cell lanes of different quads over the corners.
+    // rotated per quad (and mirrored per camera, corner_mask) so that neighbouring quads
+    // update different voxels in the same round.
     template <class Sink>
     __device__ __forceinline__ void scatter8(const Geo& G, bool on, bool inb, const Corners& c, f4 val, Sink& out) {
         if (wave_any(on && !inb)) {  // corners outside the window: straight to HBM
@@ -445,14 +455,14 @@ struct Brick4 {
         const bool keep = keep_x & !(gy & (((lane >> 3) & 1) != 0));
         const bool give_x = gx & ((lane & 1) != 0);
         const bool give_y = gy & (((lane >> 3) & 1) != 0);
-        const int phi = (((lane & 7) >> 1) + 3 * (lane >> 4)) & 7;
+        const int phi = ((((lane & 7) >> 1) << 1) + (lane >> 4)) & 7;
         const int sx0 = c.i[0] & 7, sx1 = (c.i[0] + 1) & 7;
         const int sy0 = (c.i[1] & 7) << 3, sy1 = ((c.i[1] + 1) & 7) << 3;
         const int sz0 = (c.i[2] & 7) << 6, sz1 = ((c.i[2] + 1) & 7) << 6;
         const float wx0 = 1.0f - c.f[0], wy0 = 1.0f - c.f[1], wz0 = 1.0f - c.f[2];
 #pragma unroll 1
         for (int r = 0; r < 8; ++r) {
-            const int i = (r + phi) & 7;
+            const int i = ((r + phi) & 7) ^ cmask;
             const bool bx = i & 1, by = i & 2, bz = i & 4;
             const int sl = (bz ? sz1 : sz0) + (by ? sy1 : sy0) + (bx ? sx1 : sx0);
             const float w = mine ? (bx ? c.f[0] : wx0) * (by ? c.f[1] : wy0) * (bz ? c.f[2] : wz0) : 0.0f;
@@ -530,6 +540,7 @@ struct BrickAtomic {
 // rotated by pixel position.
 struct Brick6 {
     Window win;
+    int cmask;             // corner-order mirror of the camera (corner_mask)
     volatile lds_f4* s4;   // [kB3] channels 0..3
     volatile lds_f2* s2;   // [kB3] channels 4..5
     volatile lds_u8* tag;  // [kB3] lane ids
@@ -596,14 +607,14 @@ struct Brick6 {
         const bool keep = keep_x & !(gy & (((lid >> 3) & 1) != 0));
         const bool give_x = gx & ((lid & 1) != 0);
         const bool give_y = gy & (((lid >> 3) & 1) != 0);
-        const int phi = (((lid & 7) >> 1) + 3 * (lid >> 4)) & 7;
+        const int phi = ((((lid & 7) >> 1) << 1) + (lid >> 4)) & 7;
         const int sx0 = c.i[0] & 7, sx1 = (c.i[0] + 1) & 7;
         const int sy0 = (c.i[1] & 7) << 3, sy1 = ((c.i[1] + 1) & 7) << 3;
         const int sz0 = (c.i[2] & 7) << 6, sz1 = ((c.i[2] + 1) & 7) << 6;
         const float wx0 = 1.0f - c.f[0], wy0 = 1.0f - c.f[1], wz0 = 1.0f - c.f[2];
 #pragma unroll 1
         for (int r = 0; r < 8; ++r) {
-            const int i = (r + phi) & 7;
+            const int i = ((r + phi) & 7) ^ cmask;
             const bool bx = i & 1, by = i & 2, bz = i & 4;
             const int sl = (bz ? sz1 : sz0) + (by ? sy1 : sy0) + (bx ? sx1 : sx0);
             const float w = mine ? (bx ? c.f[0] : wx0) * (by ? c.f[1] : wy0) * (bz ? c.f[2] : wz0) : 0.0f;
@@ -1388,6 +1399,7 @@ __global__ __launch_bounds__(kBlock) void k_ray(Geo G, RayArgs A) {
         if constexpr (JT) {
             Brick4 B;
             B.init(s_brick4 + wave * kB3, s_tag + wave * kB3);
+            B.cmask = corner_mask(A.cams[p.cam]);
             // the texel table borrows the head of the window's storage until it is flushed
             TT.init((int*)(s_brick4 + wave * kB3), (float*)(s_brick4 + wave * kB3 + 16));
             float u[3] = {0.0f, 0.0f, 0.0f};
@@ -1427,6 +1439,7 @@ __global__ __launch_bounds__(kBlock) void k_ray(Geo G, RayArgs A) {
         } else {
             Brick6 B;
             B.init(s_brick + wave * NCH * kB3 / 4, s_tag + wave * kB3);
+            B.cmask = corner_mask(A.cams[p.cam]);
             feature_scatter<PD>(G, r, p.active, X, depth, B, TT, A.y);
         }
     }
