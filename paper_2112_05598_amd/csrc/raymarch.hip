@@ -293,6 +293,28 @@ __device__ __forceinline__ f4 dpp_xor1(f4 v) { return f4{dpp_xor1(v.x), dpp_xor1
 __device__ __forceinline__ f4 dpp_row_xor8(f4 v) {
     return f4{dpp_row_xor8(v.x), dpp_row_xor8(v.y), dpp_row_xor8(v.z), dpp_row_xor8(v.w)};
 }
+
+// Folding of a 2x2 lane quad before an election: a lane hands its value to its x neighbour
+// (lane ^ 1), then to its y neighbour (lane ^ 8), then across the quad's diagonal (lane ^ 9),
+// each time when both are still in the election and sit in the same cell (same key); the
+// higher lane of a pair gives.  Every lane of the wave must run it (DPP swaps).
+struct QuadFolds {
+    bool give_x, give_y, give_d, keep;
+};
+__device__ __forceinline__ QuadFolds quad_folds(bool mine, int cell) {
+    const int lane = lane_id();
+    const int key = mine ? cell : -1;
+    QuadFolds q;
+    q.give_x = mine & (dpp_xor1(key) == key) & ((lane & 1) != 0);
+    const bool keep_x = mine & !q.give_x;
+    const int k2 = keep_x ? key : -1;
+    q.give_y = keep_x & (dpp_row_xor8(k2) == k2) & ((lane & 8) != 0);
+    const bool keep_y = keep_x & !q.give_y;
+    const int k3 = keep_y ? key : -1;
+    q.give_d = keep_y & (dpp_row_xor8(dpp_xor1(k3)) == k3) & ((lane & 8) != 0);
+    q.keep = keep_y & !q.give_d;
+    return q;
+}
 // explicit LDS pointers, so accesses compile to ds_* instructions rather than flat ones
 #define LDS __attribute__((address_space(3)))
 typedef LDS f4 lds_f4;
@@ -442,19 +464,9 @@ struct Brick4 {
         if (!wave_any(mine)) return;
         const int lane = lane_id();
         const unsigned char tag_id = (unsigned char)lane;
-        // which neighbours fold into this lane, and whether this lane keeps a contribution.
         // The swaps run in straight-line code with every lane active: a lane swap executed
         // under a partial mask would read the other lane's register as it was last written.
-        const int key = mine ? c.v : -1;
-        const int kx = dpp_xor1(key);
-        const bool gx = mine & (kx == key);                        // x neighbour in the same cell
-        const bool keep_x = mine & !(gx & ((lane & 1) != 0));      // the odd lane of a pair gives
-        const int key2 = keep_x ? key : -1;
-        const int ky = dpp_row_xor8(key2);
-        const bool gy = keep_x & (ky == key2);                     // y neighbour (after x) too
-        const bool keep = keep_x & !(gy & (((lane >> 3) & 1) != 0));
-        const bool give_x = gx & ((lane & 1) != 0);
-        const bool give_y = gy & (((lane >> 3) & 1) != 0);
+        const QuadFolds q = quad_folds(mine, c.v);
         const int phi = ((((lane & 7) >> 1) << 1) + (lane >> 4)) & 7;
         const int sx0 = c.i[0] & 7, sx1 = (c.i[0] + 1) & 7;
         const int sy0 = (c.i[1] & 7) << 3, sy1 = ((c.i[1] + 1) & 7) << 3;
@@ -472,10 +484,11 @@ struct Brick4 {
                 add = val * w;
                 // a donor hands its value over; every other lane hands over zero
                 const f4 zero = f4{0.0f, 0.0f, 0.0f, 0.0f};
-                add += dpp_xor1(give_x ? add : zero);
-                add += dpp_row_xor8(give_y ? add : zero);
+                add += dpp_xor1(q.give_x ? add : zero);
+                add += dpp_row_xor8(q.give_y ? add : zero);
+                add += dpp_row_xor8(dpp_xor1(q.give_d ? add : zero));
             }
-            bool pend = keep;
+            bool pend = q.keep;
             while (wave_any(pend)) {
                 if (pend) {
                     tag[sl] = tag_id;
@@ -597,16 +610,9 @@ struct Brick6 {
         if (!wave_any(mine)) return;
         const int lid = lane_id();
         const unsigned char lane = (unsigned char)lid;
-        // fold the x and y neighbours' corners into this lane when they share its cell, as the
-        // J^T scatter does (same swaps, same corner order for the lanes of a 2x2 quad)
-        const int key = mine ? c.v : -1;
-        const bool gx = mine & (dpp_xor1(key) == key);
-        const bool keep_x = mine & !(gx & ((lid & 1) != 0));
-        const int key2 = keep_x ? key : -1;
-        const bool gy = keep_x & (dpp_row_xor8(key2) == key2);
-        const bool keep = keep_x & !(gy & (((lid >> 3) & 1) != 0));
-        const bool give_x = gx & ((lid & 1) != 0);
-        const bool give_y = gy & (((lid >> 3) & 1) != 0);
+        // fold the quad's lanes that share a cell, as the J^T scatter does (same swaps, same
+        // corner order for the lanes of a 2x2 quad)
+        const QuadFolds q = quad_folds(mine, c.v);
         const int phi = ((((lid & 7) >> 1) << 1) + (lid >> 4)) & 7;
         const int sx0 = c.i[0] & 7, sx1 = (c.i[0] + 1) & 7;
         const int sy0 = (c.i[1] & 7) << 3, sy1 = ((c.i[1] + 1) & 7) << 3;
@@ -626,16 +632,20 @@ struct Brick6 {
                 b = f2{base[4], base[5]} * w;
                 const f4 z4 = f4{0.0f, 0.0f, 0.0f, 0.0f};
                 const f2 z2 = f2{0.0f, 0.0f};
-                const f4 ga = give_x ? a : z4;
-                const f2 gb = give_x ? b : z2;
+                const f4 ga = q.give_x ? a : z4;
+                const f2 gb = q.give_x ? b : z2;
                 a += dpp_xor1(ga);
                 b += f2{dpp_xor1(gb.x), dpp_xor1(gb.y)};
-                const f4 ha = give_y ? a : z4;
-                const f2 hb = give_y ? b : z2;
+                const f4 ha = q.give_y ? a : z4;
+                const f2 hb = q.give_y ? b : z2;
                 a += dpp_row_xor8(ha);
                 b += f2{dpp_row_xor8(hb.x), dpp_row_xor8(hb.y)};
+                const f4 da = q.give_d ? a : z4;
+                const f2 db = q.give_d ? b : z2;
+                a += dpp_row_xor8(dpp_xor1(da));
+                b += f2{dpp_row_xor8(dpp_xor1(db.x)), dpp_row_xor8(dpp_xor1(db.y))};
             }
-            bool pend = keep;
+            bool pend = q.keep;
             while (wave_any(pend)) {
                 if (pend) {
                     tag[sl] = lane;
