@@ -519,6 +519,10 @@ struct BrickAtomic {
         for (int i = lane_id(); i < NCH * kB3; i += 64) s[i] = 0.0f;
     }
     __device__ __forceinline__ bool inside(const int lo[3], const int hi[3]) const { return win.inside(lo, hi); }
+    // zero the first n floats (the texel table's keys after its flush)
+    __device__ __forceinline__ void clear_head(int n) {
+        for (int i = lane_id(); i < n; i += 64) s[i] = 0.0f;
+    }
     __device__ __forceinline__ void add(int x, int y, int z, const float v[NCH]) {
         const int sl = ring_slot(x, y, z);
 #pragma unroll
@@ -565,6 +569,10 @@ struct Brick6 {
         win.o[0] = win.o[1] = win.o[2] = -(1 << 24);
         float* f = (float*)base;
         for (int i = lane_id(); i < 6 * kB3; i += 64) ((volatile lds_float*)f)[i] = 0.0f;
+    }
+    // zero the first n float4 slots of the first plane (the texel table's keys after its flush)
+    __device__ __forceinline__ void clear_head(int n) {
+        for (int i = lane_id(); i < n; i += 64) s4[i] = f4{0.0f, 0.0f, 0.0f, 0.0f};
     }
     __device__ __forceinline__ bool inside(const int lo[3], const int hi[3]) const { return win.inside(lo, hi); }
     template <class F>
@@ -1130,6 +1138,7 @@ __device__ __forceinline__ void grad_scatter(const Geo& G, const Ray& r, bool li
         env_back<PD>(G, r, X, Tx, S, emit);
     }
     TT.flush(sink);
+    B.clear_head(64);  // the table's keys (its sums are left at zero by the flush)
     GradWin w;
     w.i[0] = w.i[1] = w.i[2] = 0;
     clear_slots(w, 0xFFu);
@@ -1243,6 +1252,7 @@ __device__ __forceinline__ void feature_scatter(const Geo& G, const Ray& r, bool
         env_back<PD>(G, r, X, Tx, S, emit);
     }
     TT.flush(sink);
+    B.clear_head(16);  // the table's keys (its sums are left at zero by the flush)
     float G0 = Tx * S[0], G1 = Tx * S[1], G2 = Tx * S[2];
     const int nx = G.nx, nxy = G.nx * G.ny;
     const float unit = G.h * G.step;
@@ -1348,9 +1358,7 @@ __global__ __launch_bounds__(kBlock) void k_ray(Geo G, RayArgs A) {
     constexpr bool JT = MODE == M_VJP || MODE == M_JTJ;
     __shared__ f4 s_brick[(SCATTER && !JT) ? kWaves * NCH * kB3 / 4 : 1];
     __shared__ f4 s_brick4[JT ? kWaves * kB3 : 1];
-    __shared__ unsigned char s_tag[SCATTER ? kWaves * kB3 : 1];
-    __shared__ float s_tab[(SCATTER && !JT) ? kWaves * NCH * 64 : 1];
-    __shared__ int s_keys[(SCATTER && !JT) ? kWaves * 64 : 1];
+    __shared__ unsigned char s_tag[(SCATTER && MODE != M_GRAD) ? kWaves * kB3 : 1];
     if (A.done && *A.done) return;
     const Pix p = pixel_of(G);
     const int wave = threadIdx.x >> 6;
@@ -1404,13 +1412,13 @@ __global__ __launch_bounds__(kBlock) void k_ray(Geo G, RayArgs A) {
             if (aux) A.rout[nres * p.ray + 3] = dr4 * Tdexit;  // d r4 = dr4/dT * dT
         }
     } else if constexpr (SCATTER) {
+        // the texel hash table of each pass borrows the head of its window's storage until it
+        // is flushed (keys: 64 ints, then NCH x 64 sums)
         TexTable<NCH> TT;
-        if constexpr (!JT) TT.init(s_keys + wave * 64, s_tab + wave * NCH * 64);
         if constexpr (JT) {
             Brick4 B;
             B.init(s_brick4 + wave * kB3, s_tag + wave * kB3);
             B.cmask = corner_mask(A.cams[p.cam]);
-            // the texel table borrows the head of the window's storage until it is flushed
             TT.init((int*)(s_brick4 + wave * kB3), (float*)(s_brick4 + wave * kB3 + 16));
             float u[3] = {0.0f, 0.0f, 0.0f};
             float u4 = 0.0f;
@@ -1434,6 +1442,7 @@ __global__ __launch_bounds__(kBlock) void k_ray(Geo G, RayArgs A) {
         } else if constexpr (MODE == M_GRAD) {
             BrickAtomic<NCH> B;
             B.init((float*)(s_brick + wave * NCH * kB3 / 4));
+            TT.init((int*)(s_brick + wave * NCH * kB3 / 4), (float*)(s_brick + wave * NCH * kB3 / 4) + 64);
             float res[3] = {0.0f, 0.0f, 0.0f};
             if (p.active && A.targets) {
 #pragma unroll
@@ -1449,6 +1458,7 @@ __global__ __launch_bounds__(kBlock) void k_ray(Geo G, RayArgs A) {
         } else {
             Brick6 B;
             B.init(s_brick + wave * NCH * kB3 / 4, s_tag + wave * kB3);
+            TT.init((int*)(s_brick + wave * NCH * kB3 / 4), (float*)(s_brick + wave * NCH * kB3 / 4) + 64);
             B.cmask = corner_mask(A.cams[p.cam]);
             feature_scatter<PD>(G, r, p.active, X, depth, B, TT, A.y);
         }
