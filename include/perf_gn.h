@@ -197,6 +197,7 @@ int32_t perf_apply_JtJ(perf_scene* s, const void* d_x, const float* d_v, float* 
  * kind      PERF_PRECOND_JACOBI: d_out [P] = 1/diag(J^T J) (0 where the diagonal is 0);
  *           PERF_PRECOND_BLOCK4: d_out [units][10] = upper triangle (00,01,02,03,11,12,13,22,23,33)
  *           of the inverse of each block after a ridge of 1e-6 max(d, f) (0 for empty units);
+ *           inverses beyond the FP32 range are taken as 0 (perf_invert_blocks);
  *           PERF_PRECOND_NONE: d_out ignored.
  * d_F       device double[1], may be NULL.
  */
@@ -251,6 +252,19 @@ int32_t perf_upsample(const perf_scene_desc* from, const float* d_from, const pe
  * of the J^T J v kernel with this probe's.  d_y [n * stride] is caller-owned; asynchronous.
  */
 int32_t perf_atomic_probe(float* d_y, int64_t n, int32_t reps, int32_t stride, void* stream);
+
+/*
+ * Preconditioner inverse from given blocks (Sec. III-G), the step perf_build_precond ends with.
+ * d_blocks  device float [units][5] = (d, e_r, e_g, e_b, f) of [[d I3, e], [e^T, f]].
+ * kind      PERF_PRECOND_JACOBI: d_out [units][4] = (1/d, 1/d, 1/d, 1/f), 0 for a zero diagonal;
+ *           PERF_PRECOND_BLOCK4: d_out [units][10] = upper triangle (00,01,02,03,11,12,13,22,23,33)
+ *           of the inverse after a ridge of 1e-6 max(d, f), 0 for an empty unit.
+ *           An inverse entry beyond the FP32 range (a diagonal in the subnormal range) makes the
+ *           entry (Jacobi) or the unit (block) 0, as for an empty one.
+ * Caller-owned device memory; asynchronous on stream.  PERF_EINVAL for a null pointer with
+ * units > 0, units < 0 or another kind.
+ */
+int32_t perf_invert_blocks(const float* d_blocks, int64_t units, int32_t kind, float* d_out, void* stream);
 
 /* Round FP32 parameters to bfloat16 storage (round to nearest even): d_out[n] uint16. */
 int32_t perf_pack_bf16(const float* d_in, uint16_t* d_out, int64_t n, void* stream);

@@ -399,6 +399,15 @@ int32_t perf_atomic_probe(float* d_y, int64_t n, int32_t reps, int32_t stride, v
     return PERF_OK;
 }
 
+int32_t perf_invert_blocks(const float* d_blocks, int64_t units, int32_t kind, float* d_out, void* stream) {
+    if (units < 0) return fail(PERF_EINVAL, "negative unit count");
+    if ((!d_blocks || !d_out) && units > 0) return fail(PERF_EINVAL, "null argument");
+    if (kind != PERF_PRECOND_JACOBI && kind != PERF_PRECOND_BLOCK4) return fail(PERF_EINVAL, "kind must be JACOBI or BLOCK4");
+    if (units == 0) return PERF_OK;
+    CK(launch_precond_invert(kind, d_blocks, units, d_out, (hipStream_t)stream));
+    return PERF_OK;
+}
+
 int32_t perf_pack_bf16(const float* d_in, uint16_t* d_out, int64_t n, void* stream) {
     if ((!d_in || !d_out) && n > 0) return fail(PERF_EINVAL, "null argument");
     if (n < 0) return fail(PERF_EINVAL, "negative size");

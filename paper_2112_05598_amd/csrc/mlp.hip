@@ -13,6 +13,7 @@
 // B[4(l/32)+j][l%32], j < 4; result register v of lane l is C[8(v/4)+4(l/32)+v%4][l%32].
 #include "perf_internal.h"
 
+#include <cfloat>
 #include <math.h>
 
 namespace perf {
@@ -226,6 +227,8 @@ __global__ __launch_bounds__(64 * kInferWaves) void k_mlp_infer(const unsigned s
                 const float rho = kRidge * m;
                 const float sd = 1.0f / sqrtf(d + rho), sf = 1.0f / sqrtf(f + rho);
                 const float ds[4] = {sd, sd, sd, sf};
+                float ov[10];
+                bool fits = true;
                 int k = 0;
 #pragma unroll
                 for (int i = 0; i < 4; ++i)
@@ -234,8 +237,12 @@ __global__ __launch_bounds__(64 * kInferWaves) void k_mlp_infer(const unsigned s
                         float p = 0.0f;
 #pragma unroll
                         for (int q = 0; q < 4; ++q) p += L[i][q] * L[j][q];
-                        o[k] = ds[i] * ds[j] * p;
+                        ov[k] = ds[i] * ds[j] * p;
+                        fits &= fabsf(ov[k]) <= FLT_MAX;
                     }
+                // a unit whose inverse does not fit FP32 is taken as empty, as for the exact inverses
+#pragma unroll
+                for (int i = 0; i < 10; ++i) o[i] = fits ? ov[i] : 0.0f;
             }
         }
     }

@@ -8,6 +8,7 @@
 // of the solve checks, so the host can enqueue a whole solve without reading anything back.
 #include "perf_internal.h"
 
+#include <cfloat>
 #include <math.h>
 
 namespace perf {
@@ -101,8 +102,11 @@ __global__ void k_invert(int kind, const float* __restrict__ blocks, int64_t uni
         const float* b = blocks + 5 * u;
         const double d = b[0], e0 = b[1], e1 = b[2], e2 = b[3], f = b[4];
         if (kind == PERF_PRECOND_JACOBI) {
-            const float id = d > 0.0 ? (float)(1.0 / d) : 0.0f;
-            const float iff = f > 0.0 ? (float)(1.0 / f) : 0.0f;
+            // an inverse that does not fit FP32 (a diagonal in the subnormal range, from a unit
+            // seen only through near-opaque matter) is taken as 0 like an empty diagonal
+            const double rd = 1.0 / d, rf = 1.0 / f;
+            const float id = (d > 0.0 && rd <= (double)FLT_MAX) ? (float)rd : 0.0f;
+            const float iff = (f > 0.0 && rf <= (double)FLT_MAX) ? (float)rf : 0.0f;
             reinterpret_cast<float4*>(out)[u] = make_float4(id, id, id, iff);
         } else {
             float* o = out + 10 * u;
@@ -116,16 +120,14 @@ __global__ void k_invert(int kind, const float* __restrict__ blocks, int64_t uni
             const double dd = d + rho, ff = f + rho;
             const double s = ff - (e0 * e0 + e1 * e1 + e2 * e2) / dd;  // Schur complement of d I
             const double id = 1.0 / dd, is = 1.0 / s, k = id * id * is;
-            o[0] = (float)(id + e0 * e0 * k);
-            o[1] = (float)(e0 * e1 * k);
-            o[2] = (float)(e0 * e2 * k);
-            o[3] = (float)(-e0 * id * is);
-            o[4] = (float)(id + e1 * e1 * k);
-            o[5] = (float)(e1 * e2 * k);
-            o[6] = (float)(-e1 * id * is);
-            o[7] = (float)(id + e2 * e2 * k);
-            o[8] = (float)(-e2 * id * is);
-            o[9] = (float)is;
+            const double v[10] = {id + e0 * e0 * k, e0 * e1 * k,      e0 * e2 * k, -e0 * id * is, id + e1 * e1 * k,
+                                  e1 * e2 * k,      -e1 * id * is,    id + e2 * e2 * k, -e2 * id * is, is};
+            // a unit whose inverse does not fit FP32 is taken as empty (as for the Jacobi case)
+            bool fits = true;
+#pragma unroll
+            for (int i = 0; i < 10; ++i) fits &= fabs(v[i]) <= (double)FLT_MAX;
+#pragma unroll
+            for (int i = 0; i < 10; ++i) o[i] = fits ? (float)v[i] : 0.0f;
         }
     }
 }

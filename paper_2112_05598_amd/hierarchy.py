@@ -60,7 +60,7 @@ def gn_hierarchy(spec, cams, targets: torch.Tensor, x0: torch.Tensor, levels: in
             st = sc.gn_step(x, max_iters=pcg_iters, precond=precond)
             torch.cuda.synchronize()
             recs.append({"level": k, "grid": sp.nx, "F_before": st["F_before"], "F_after": st["F_after"],
-                         "pcg_iters": st["pcg_iters"], "ms": (time.perf_counter() - t0) * 1e3})
+                         "pcg_iters": st["pcg_iters"], "flags": st["flags"], "ms": (time.perf_counter() - t0) * 1e3})
             log(f"[hierarchy] level {k} ({sp.nx}x{sp.ny}x{sp.nz}, layers {sp.env_w}x{sp.env_h}): "
                 f"F {st['F_before']:.6g} -> {st['F_after']:.6g}")
             if F_stop >= 0 and k == levels - 1 and st["F_after"] <= F_stop:

@@ -263,3 +263,20 @@ def upsample(spec_from, x_from: torch.Tensor, spec_to, out: Optional[torch.Tenso
     st = ctypes.c_void_p(torch.cuda.current_stream(x_from.device).cuda_stream) if stream is None else stream
     abi.check(lib.perf_upsample(ctypes.byref(d_from), _ptr(x_from), ctypes.byref(d_to), _ptr(out), st))
     return out
+
+
+def invert_blocks(blocks: torch.Tensor, kind: str = "jacobi", stream=None) -> torch.Tensor:
+    """Preconditioner inverse of given (d, e_r, e_g, e_b, f) blocks [units, 5] (perf_invert_blocks):
+    [units, 4] Jacobi entries or [units, 10] upper triangles of the ridged block inverses."""
+    lib = abi.load()
+    if blocks.dtype != torch.float32 or not blocks.is_cuda or not blocks.is_contiguous() or blocks.dim() != 2 \
+            or blocks.shape[1] != 5:
+        raise ValueError("blocks must be a contiguous float32 device tensor of shape [units, 5]")
+    k = _PRECOND[kind]
+    width = {abi.PERF_PRECOND_JACOBI: 4, abi.PERF_PRECOND_BLOCK4: 10}.get(k)
+    if width is None:
+        raise ValueError("kind must be 'jacobi' or 'block'")
+    out = torch.empty(blocks.shape[0], width, dtype=torch.float32, device=blocks.device)
+    st = ctypes.c_void_p(torch.cuda.current_stream(blocks.device).cuda_stream) if stream is None else stream
+    abi.check(lib.perf_invert_blocks(_ptr(blocks), blocks.shape[0], k, _ptr(out), st))
+    return out

@@ -386,6 +386,28 @@ def test_block_inverse_is_inverse(oracle_mod):
     np.testing.assert_allclose(jac[20:24], [1 / d[5]] * 3 + [1 / f[5]])
 
 
+def test_inverses_beyond_fp32_are_empty(oracle_mod):
+    """A diagonal in the FP32 subnormal range has an inverse beyond the FP32 range: the unit (block)
+    or the entry (Jacobi) is then 0, as an empty one; a small normal diagonal is inverted."""
+    fmax = float(np.finfo(np.float32).max)
+    blocks = np.array([[1e-40, 0.0, 0.0, 0.0, 2.0],    # tiny d, normal f
+                       [1e-30, 0.0, 0.0, 0.0, 1e-30],  # small but invertible
+                       [1e-41, 1e-42, 0.0, 0.0, 1e-41],
+                       [2.0, 0.5, 0.0, 0.0, 1.0]])
+    jac = oracle_mod.jacobi_inverse(blocks).reshape(-1, 4)
+    assert np.all(jac[0, :3] == 0) and jac[0, 3] == 0.5
+    np.testing.assert_allclose(jac[1], 1e30, rtol=1e-12)
+    assert np.all(jac[2] == 0)
+    np.testing.assert_allclose(jac[3], [0.5, 0.5, 0.5, 1.0])
+    binv = oracle_mod.block_inverse(blocks)
+    assert np.all(binv[2] == 0)  # both diagonals subnormal: the ridge cannot lift them into range
+    assert np.all(np.abs(binv) <= fmax)
+    B = oracle_mod.block_matrix(blocks)
+    for i in (0, 1, 3):  # unit 0: the ridge 1e-6 max(d, f) keeps the inverse in range
+        m = max(blocks[i, 0], blocks[i, 4])
+        np.testing.assert_allclose((B[i] + 1e-6 * m * np.eye(4)) @ binv[i], np.eye(4), atol=1e-9)
+
+
 # ----------------------------------------------------------------------------- Alg. 2
 
 def _spd(n, rank, seed):
