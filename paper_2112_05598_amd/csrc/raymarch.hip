@@ -397,12 +397,12 @@ struct Window {
 };
 
 // The J^T accumulator: float4 (three colour channels and sigma) per window voxel.  LDS
-// float atomics are slow when many lanes of an instruction add, so updates are plain
-// read-modify-writes by one elected lane per slot: every pending lane writes its lane id
-// into the slot's tag, the lanes that read their own id back own a distinct slot this
-// round and update it, the others retry.  Each lane visits its eight corners in an order
-// rotated by its pixel position, so lanes of one cell (which share all eight corners)
-// mostly target different voxels in the same round.
+// float atomics are slow on this hardware even without address conflicts, so updates are
+// plain read-modify-writes by one elected lane per slot: every pending lane writes its lane
+// id into the slot's tag and reads the tag and the slot back in one batch; the lanes that
+// read their own id own a distinct slot this round and write the sum, the others retry.
+// Lanes of one cell are folded into one (quad_folds); lanes of neighbouring cells visit
+// the corners in orders chosen so that they target different voxels in the same round.
 struct Brick4 {
     Window win;
     int cmask;            // corner-order mirror of the camera (corner_mask)
@@ -440,13 +440,12 @@ struct Brick4 {
         win.each_voxel(fl);
     }
     // add val * weight(corner) to the 8 corners of every lane that is on (uniform call).
-    // Lanes of one grid cell share all eight corners.  Before the election, each lane adds in
-    // the contribution of its x neighbour (lane ^ 1) and then of its y neighbour (lane ^ 8)
-    // when they sit in the same cell, through DPP lane swaps, so one lane per combined group
-    // enters the election.  Lanes of different cells never target one voxel with the same
-    // corner index, so every lane of a 2x2 lane quad visits the corners in the same order,
-    // rotated per quad (and mirrored per camera, corner_mask) so that neighbouring quads
-    // update different voxels in the same round.
+    // Lanes of one grid cell share all eight corners.  Before the election, the lanes of a
+    // 2x2 quad that sit in one cell fold their contributions into one lane (quad_folds, DPP
+    // lane swaps), so one lane per group enters the election.  Lanes of different cells
+    // never target one voxel with the same corner index, so every lane of a 2x2 lane quad
+    // visits the corners in the same order, rotated per quad (and mirrored per camera,
+    // corner_mask) so that neighbouring quads update different voxels in the same round.
     template <class Sink>
     __device__ __forceinline__ void scatter8(const Geo& G, bool on, bool inb, const Corners& c, f4 val, Sink& out) {
         if (wave_any(on && !inb)) {  // corners outside the window: straight to HBM
@@ -553,8 +552,7 @@ struct BrickAtomic {
 };
 
 // The feature pass's accumulator: 6 channels per window voxel (a float4 and a float2 plane),
-// updated like Brick4 by elected read-modify-writes, eight corners per sample in an order
-// rotated by pixel position.
+// updated like Brick4: quad folds, then elected read-modify-writes in Brick4's corner order.
 struct Brick6 {
     Window win;
     int cmask;             // corner-order mirror of the camera (corner_mask)
