@@ -471,13 +471,12 @@ struct Brick4 {
         const int sy0 = (c.i[1] & 7) << 3, sy1 = ((c.i[1] + 1) & 7) << 3;
         const int sz0 = (c.i[2] & 7) << 6, sz1 = ((c.i[2] + 1) & 7) << 6;
         const float wx0 = 1.0f - c.f[0], wy0 = 1.0f - c.f[1], wz0 = 1.0f - c.f[2];
-#pragma unroll 1
-        for (int r = 0; r < 8; ++r) {
+        // the next corner's slot and value are formed while this corner's first round waits on LDS
+        auto corner = [&](int r, int& sl, f4& add) {
             const int i = ((r + phi) & 7) ^ cmask;
             const bool bx = i & 1, by = i & 2, bz = i & 4;
-            const int sl = (bz ? sz1 : sz0) + (by ? sy1 : sy0) + (bx ? sx1 : sx0);
+            sl = (bz ? sz1 : sz0) + (by ? sy1 : sy0) + (bx ? sx1 : sx0);
             const float w = mine ? (bx ? c.f[0] : wx0) * (by ? c.f[1] : wy0) * (bz ? c.f[2] : wz0) : 0.0f;
-            f4 add;
             {
 #pragma clang fp contract(off)
                 add = val * w;
@@ -487,19 +486,41 @@ struct Brick4 {
                 add += dpp_row_xor8(q.give_y ? add : zero);
                 add += dpp_row_xor8(dpp_xor1(q.give_d ? add : zero));
             }
+        };
+        int sl;
+        f4 add;
+        corner(0, sl, add);
+#pragma unroll 1
+        for (int r = 0; r < 8; ++r) {
             bool pend = q.keep;
+            unsigned char t = 0;
+            f4 cur = f4{0.0f, 0.0f, 0.0f, 0.0f};
+            if (pend) {
+                tag[sl] = tag_id;
+                t = tag[sl];
+                cur = s[sl];
+            }
+            int sl_n = 0;
+            f4 add_n = f4{0.0f, 0.0f, 0.0f, 0.0f};
+            if (r < 7) corner(r + 1, sl_n, add_n);
+            if (pend && t == tag_id) {
+                s[sl] = cur + add;
+                pend = false;
+            }
             while (wave_any(pend)) {
                 if (pend) {
                     tag[sl] = tag_id;
                     // read the slot with the tag, so a round waits on LDS once
-                    const unsigned char t = tag[sl];
-                    const f4 cur = s[sl];
-                    if (t == tag_id) {
-                        s[sl] = cur + add;
+                    const unsigned char t2 = tag[sl];
+                    const f4 c2 = s[sl];
+                    if (t2 == tag_id) {
+                        s[sl] = c2 + add;
                         pend = false;
                     }
                 }
             }
+            sl = sl_n;
+            add = add_n;
         }
     }
 };
