@@ -135,3 +135,17 @@ def test_upsample_rejects_mismatched_levels():
         assert rc == abi.PERF_EINVAL, (sf, st, rc)
     rc = lib.perf_upsample(ctypes.byref(make_desc(a, 1, 1)), None, ctypes.byref(make_desc(a, 1, 1)), fake, None)
     assert rc == abi.PERF_EINVAL
+
+
+def test_invert_blocks_rejects_bad_arguments_before_device_work():
+    """perf_invert_blocks validates its arguments before any launch; zero units is a no-op."""
+    import ctypes
+    from paper_2112_05598_amd import abi
+    lib = abi.load()
+    fake = ctypes.c_void_p(256)  # never dereferenced: every case below returns before a launch
+    assert lib.perf_invert_blocks(None, 4, abi.PERF_PRECOND_JACOBI, fake, None) == abi.PERF_EINVAL
+    assert lib.perf_invert_blocks(fake, 4, abi.PERF_PRECOND_BLOCK4, None, None) == abi.PERF_EINVAL
+    assert lib.perf_invert_blocks(fake, -1, abi.PERF_PRECOND_JACOBI, fake, None) == abi.PERF_EINVAL
+    for kind in (abi.PERF_PRECOND_NONE, abi.PERF_PRECOND_LEARNED, 17):
+        assert lib.perf_invert_blocks(fake, 4, kind, fake, None) == abi.PERF_EINVAL
+    assert lib.perf_invert_blocks(None, 0, abi.PERF_PRECOND_JACOBI, None, None) == abi.PERF_OK
