@@ -94,8 +94,8 @@ def main():
                     help="skip the learned-preconditioner GN run to the Jacobi run's final objective")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (the ray-sharded design is "
-              "described, not built); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (sharding the rays over GPUs "
+              "is a design, not implemented); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -61,7 +61,7 @@ enum {
     PERF_ENOMEM = -2,      /* workspace smaller than perf_workspace_bytes() */
     PERF_EDEVICE = -3,     /* a HIP runtime call failed */
     PERF_ENUMERIC = -4,    /* non-finite input found (only with checks = 1) */
-    PERF_EUNSUPPORTED = -5 /* option not supported by this build / descriptor */
+    PERF_EUNSUPPORTED = -5 /* option not supported by the library / descriptor */
 };
 
 enum { PERF_F32 = 0, PERF_BF16 = 1 };

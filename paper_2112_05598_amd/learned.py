@@ -1,4 +1,4 @@
-"""Training and evaluation driver of the learned block preconditioner.
+"""Training and evaluation code of the learned block preconditioner.
 
 Training data: exact 4x4 blocks of J^T J and per-unit features computed by the library
 along Gauss-Newton trajectories (Jacobi-preconditioned steps 1..5) of seeded scenes of the

@@ -1,4 +1,4 @@
-"""Profiling driver for the J^T J v kernel and its HBM-traffic summary.
+"""Profiling script for the J^T J v kernel and its HBM-traffic summary.
 
   run:        python -m paper_2112_05598_amd.profile_jtj run --workload cfg2 --launches 3 --copy-mib 2048 \
                   [--timing-json T.json]

@@ -49,7 +49,7 @@ def main():
     ap.add_argument("--gn-eval", default="20000:20005", help="held-out seeds of the GN time-to-F comparison")
     ap.add_argument("--gn-steps-eval", type=int, default=5)
     ap.add_argument("--gn-pcg", type=int, default=30)
-    ap.add_argument("--out", default="gpurun_out/learned")
+    ap.add_argument("--out", default="learned_out")
     args = ap.parse_args()
     os.makedirs(args.out, exist_ok=True)
     log = lambda m: print(m, flush=True)  # noqa: E731

@@ -73,7 +73,7 @@ def test_two_level_gn_transition(oracle_mod):
     assert F1_or <= 1.5 * F[-1]
     st = sc1.gn_step(x1, max_iters=10)
     assert st["F_after"] < st["F_before"]
-    # the driver runs the same schedule end to end
+    # hierarchy.py's command line runs the same schedule end to end
     xh, recs = gn_hierarchy(w.spec, w.cams, t, torch.from_numpy(ps.init_params(s0)).cuda(), 2, [3, 1], 10)
     assert [r["level"] for r in recs] == [0, 0, 0, 1]
     assert recs[-1]["F_after"] < recs[0]["F_before"]

@@ -4,7 +4,8 @@ size and environment layers, 8 cameras at 200x200 framing the crop).
 Gated: the GPU's bfloat16 packing is bit-exact (round to nearest even); the FP32 path matches
 the FP64 oracle at x; the BF16 path matches the oracle evaluated at the bf16-rounded x to the
 FP32 tolerances (same arithmetic on rounded parameters).  Reported: every result of both paths
-against the oracle at the unrounded x, written to gpurun_out/precision_cfg3_crop.md.
+against the oracle at the unrounded x, printed as a table (and written to
+$PERF_REPORT_DIR/precision_cfg3_crop.md when that variable is set).
 """
 import os
 
@@ -78,8 +79,11 @@ def test_precision_fp32_and_bf16(crop):
         rows.append((k, e32, e16_same, e16))
         assert e32 <= tol[k], (k, e32)
         assert e16_same <= tol[k], (k, e16_same)
-    os.makedirs("gpurun_out", exist_ok=True)
-    with open("gpurun_out/precision_cfg3_crop.md", "w") as f:
-        f.write("| result | FP32 vs oracle(x) | BF16 vs oracle(bf16(x)) | BF16 vs oracle(x) |\n|---|---|---|---|\n")
-        for k, a, b, c in rows:
-            f.write(f"| {k} | {a:.2e} | {b:.2e} | {c:.2e} |\n")
+    table = "| result | FP32 vs oracle(x) | BF16 vs oracle(bf16(x)) | BF16 vs oracle(x) |\n|---|---|---|---|\n"
+    table += "".join(f"| {k} | {a:.2e} | {b:.2e} | {c:.2e} |\n" for k, a, b, c in rows)
+    print(table, flush=True)
+    out_dir = os.environ.get("PERF_REPORT_DIR")
+    if out_dir:
+        os.makedirs(out_dir, exist_ok=True)
+        with open(os.path.join(out_dir, "precision_cfg3_crop.md"), "w") as f:
+            f.write(table)

@@ -1,4 +1,4 @@
-"""The atomic-throughput probe used by the profiling driver adds exactly reps to every element."""
+"""The atomic-throughput probe used by the profiling script adds exactly reps to every element."""
 import pytest
 
 pytestmark = pytest.mark.gpu

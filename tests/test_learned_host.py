@@ -1,4 +1,4 @@
-"""Host-side pieces of the learned preconditioner driver (CPU only)."""
+"""Host-side pieces of the learned preconditioner's training code (CPU only)."""
 import numpy as np
 
 
@@ -21,7 +21,7 @@ def test_fold_normalisation_matches_standardised_inputs(oracle_mod):
 
 
 def test_initial_weights_are_jacobi(oracle_mod):
-    """The driver's initial network outputs L = I for any input."""
+    """The initial network of the training code outputs L = I for any input."""
     from oracle import mlp
     from paper_2112_05598_amd.learned import init_weights
     feat = np.random.default_rng(0).normal(size=(20, 12)) * 10
