@@ -1,0 +1,94 @@
+"""Parity at the benchmark's own size: the 128^3 grid, 3 layers of 256x128, 100 cameras of
+400x400 (16 M rays), in the launch configuration bench.py times.
+
+* Per-ray outputs (residuals, J v) on all 16 M rays against the FP64 oracle on a strided
+  sample of 4000 rays: residuals 1e-5, J v 1e-4 (norm-wise over the sample).
+* The adjoint identity <u, J v> = <J^T u, v> over all rays (a property at any size), 1e-5.
+* J^T J v, the gradient and the 4x4 blocks of two whole 400x400 cameras over the full grid
+  against the oracle over the same 320 000 rays, 1e-4.
+Targets are seeded uniform images, inputs to both sides.
+"""
+import numpy as np
+import pytest
+
+import perf_synth as ps
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64).reshape(-1)
+    b = np.asarray(b, dtype=np.float64).reshape(-1)
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+@pytest.fixture(scope="module")
+def full():
+    w = ps.workload("cfg2")
+    print(f"[fullsize] cfg2: {w.cams.n} cameras {w.cams.width}x{w.cams.height}, grid {w.spec.nx}^3", flush=True)
+    rng = np.random.default_rng(2024)
+    targets = rng.uniform(0.0, 1.0, size=(w.cams.n_rays, 3)).astype(np.float32)
+    x = (0.5 * (w.x_init.astype(np.float64) + w.x_gt.astype(np.float64))).astype(np.float32)
+    return w, targets, x
+
+
+def test_sampled_rays_match_oracle(full):
+    import oracle
+    from paper_2112_05598_amd.scene import Scene
+    w, targets, x = full
+    dev = torch.device("cuda:0")
+    sc = Scene(w.spec, w.cams, torch.from_numpy(targets.reshape(-1)).to(dev), device="cuda:0")
+    tx = torch.from_numpy(x).to(dev)
+    v = ps.random_vector(sc.n_params, 21)
+    r, F = sc.render_residuals(tx)
+    u = sc.apply_J(tx, torch.from_numpy(v).to(dev))
+    torch.cuda.synchronize()
+    sample = np.arange(0, w.cams.n_rays, w.cams.n_rays // 4000, dtype=np.int64)
+    orc = oracle.OracleScene(w.spec, w.cams)
+    x64 = x.astype(np.float64)
+    _, r_or, _, _ = orc.render(x64, targets, rays=sample)
+    u_or = orc.apply_J(x64, v.astype(np.float64), rays=sample)
+    r_gpu = r.view(-1, 3).cpu().numpy()[sample]
+    u_gpu = u.view(-1, 3).cpu().numpy()[sample]
+    assert rel(r_gpu, r_or) <= 1e-5
+    assert rel(u_gpu, u_or) <= 1e-4
+
+
+def test_adjoint_identity_at_full_size(full):
+    from paper_2112_05598_amd.scene import Scene
+    w, targets, x = full
+    dev = torch.device("cuda:0")
+    sc = Scene(w.spec, w.cams, torch.from_numpy(targets.reshape(-1)).to(dev), device="cuda:0")
+    tx = torch.from_numpy(x).to(dev)
+    v = torch.from_numpy(ps.random_vector(sc.n_params, 22)).to(dev)
+    u = torch.from_numpy(ps.random_vector(3 * sc.n_rays, 23)).to(dev)
+    Jv = sc.apply_J(tx, v)
+    Jtu = sc.apply_Jt(tx, u)
+    lhs = torch.dot(u.double(), Jv.double()).item()
+    rhs = torch.dot(Jtu.double(), v.double()).item()
+    scale = torch.linalg.norm(u.double()).item() * torch.linalg.norm(Jv.double()).item()
+    assert abs(lhs - rhs) <= 1e-5 * scale, (lhs, rhs, scale)
+
+
+def test_two_whole_cameras_match_oracle(full):
+    import oracle
+    from paper_2112_05598_amd.scene import Scene
+    w, targets, x = full
+    sub = [0, 37]
+    cams = w.cams.subset(sub)
+    tg = np.ascontiguousarray(targets.reshape(w.cams.n, -1, 3)[sub].reshape(-1, 3))
+    dev = torch.device("cuda:0")
+    sc = Scene(w.spec, cams, torch.from_numpy(tg.reshape(-1)).to(dev), device="cuda:0")
+    tx = torch.from_numpy(x).to(dev)
+    v = ps.random_vector(sc.n_params, 24)
+    y = sc.apply_JtJ(tx, torch.from_numpy(v).to(dev)).cpu().numpy()
+    grad, blocks, _, F = sc.build_precond(tx, "jacobi")
+    orc = oracle.OracleScene(w.spec, cams)
+    x64 = x.astype(np.float64)
+    assert rel(y, orc.apply_JtJ(x64, v.astype(np.float64))) <= 1e-4
+    g_or, b_or, F_or = orc.grad_blocks(x64, tg)
+    assert rel(grad.cpu().numpy(), g_or) <= 1e-4
+    assert rel(blocks.cpu().numpy(), b_or) <= 1e-4
+    assert abs(F.item() - F_or) <= 1e-5 * F_or
