@@ -174,6 +174,15 @@ __device__ __forceinline__ void corners(const Geo& G, const float g[3], Corners&
     c.w[7] = wx1 * a11;
 }
 
+// the lower-corner voxel corners() would give for the grid coordinates g
+__device__ __forceinline__ int cell_key(const Geo& G, const float g[3]) {
+    const int n[3] = {G.nx, G.ny, G.nz};
+    int i[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) i[a] = min((int)fminf(fmaxf(g[a], 0.0f), (float)(n[a] - 1)), n[a] - 2);
+    return (i[2] * G.ny + i[1]) * G.nx + i[0];
+}
+
 __device__ __forceinline__ int corner_off(int j, int nx, int nxy) { return (j & 1) + ((j >> 1) & 1) * nx + (j >> 2) * nxy; }
 
 struct Tex {
@@ -447,13 +456,19 @@ struct Brick4 {
     // visits the corners in the same order, rotated per quad (and mirrored per camera,
     // corner_mask) so that neighbouring quads update different voxels in the same round.
     template <class Sink>
-    __device__ __forceinline__ void scatter8(const Geo& G, bool on, bool inb, const Corners& c, f4 val, Sink& out) {
+    __device__ __forceinline__ void scatter8(const Geo& G, bool on, bool inb, const Corners& c, f4 val, bool two,
+                                             f4 val2, const float f2[3], Sink& out) {
+        // two: a second sample of the same cell (fractional position f2) is added with this one
+        const float v2x0 = 1.0f - f2[0], v2y0 = 1.0f - f2[1], v2z0 = 1.0f - f2[2];
+        auto w2_of = [&](int i) {
+            return two ? ((i & 1) ? f2[0] : v2x0) * ((i & 2) ? f2[1] : v2y0) * ((i & 4) ? f2[2] : v2z0) : 0.0f;
+        };
         if (wave_any(on && !inb)) {  // corners outside the window: straight to HBM
             if (on && !inb) {
 #pragma unroll
                 for (int i = 0; i < 8; ++i) {
                     const int x = c.i[0] + (i & 1), y = c.i[1] + ((i >> 1) & 1), z = c.i[2] + (i >> 2);
-                    const f4 add = val * c.w[i];
+                    const f4 add = val * c.w[i] + val2 * w2_of(i);
                     const float vv[4] = {add.x, add.y, add.z, add.w};
                     out((z * G.ny + y) * G.nx + x, vv);
                 }
@@ -477,9 +492,11 @@ struct Brick4 {
             const bool bx = i & 1, by = i & 2, bz = i & 4;
             sl = (bz ? sz1 : sz0) + (by ? sy1 : sy0) + (bx ? sx1 : sx0);
             const float w = mine ? (bx ? c.f[0] : wx0) * (by ? c.f[1] : wy0) * (bz ? c.f[2] : wz0) : 0.0f;
+            const float w2 = mine ? w2_of(i) : 0.0f;
+            const f4 a0 = val * w + val2 * w2;
             {
 #pragma clang fp contract(off)
-                add = val * w;
+                add = a0;
                 // a donor hands its value over; every other lane hands over zero
                 const f4 zero = f4{0.0f, 0.0f, 0.0f, 0.0f};
                 add += dpp_xor1(q.give_x ? add : zero);
@@ -997,6 +1014,12 @@ __device__ __forceinline__ void adjoint_scatter(const Geo& G, const Ray& r, bool
     const float t_max = wave_max_f(r.K > 0 ? r.tf : -INFINITY);
     const int off = r.K > 0 ? (int)((t_max - r.tf) / unit + 0.5f) : 0;
     const int J = wave_max_i(r.K > 0 ? off + r.K : 0);
+    // A lane whose next sample lies in the same cell hands this sample's value to the next
+    // step, which scatters both together (one deferred sample at most): fewer updates enter
+    // the elections.
+    bool dpend = false;
+    f4 dval = f4{0.0f, 0.0f, 0.0f, 0.0f};
+    float df[3] = {0.0f, 0.0f, 0.0f};
     for (int j = 0; j < J; ++j) {
         const int m = j - off;
         const bool on = m >= 0 && m < r.K;
@@ -1030,7 +1053,21 @@ __device__ __forceinline__ void adjoint_scatter(const Geo& G, const Ray& r, bool
             Tn = T;
             val = f4{A * u[0], A * u[1], A * u[2], ds};
         }
-        B.scatter8(G, on, on && B.win.inside(lo, hi), c, val, sink);
+        bool defer = false;
+        if (on && !dpend && k > 0) {
+            float gn[3];
+            (void)sample_at(G, r, k - 1, gn);
+            defer = cell_key(G, gn) == c.v;
+        }
+        const bool two = on && dpend;
+        B.scatter8(G, on && !defer, on && !defer && B.win.inside(lo, hi), c, val, two, dval, df, sink);
+        if (defer) {
+            dval = val;
+            df[0] = c.f[0];
+            df[1] = c.f[1];
+            df[2] = c.f[2];
+        }
+        dpend = defer;
     }
     B.flush_all(G, sink);
 }
