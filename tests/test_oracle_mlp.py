@@ -147,3 +147,17 @@ def test_feature_sums_identities(oracle_mod):
     H, _, _, Te = sc.render(x)
     assert sums[:, 1].sum() >= totT - 1e-9
     assert np.all(sums[:, 0] >= 0) and np.all(sums[:, 1] <= sums[:, 0] + 1e-12)
+
+
+def test_inverse_beyond_fp32_is_empty(mlp):
+    """A unit whose learned inverse would exceed the FP32 range (subnormal diagonals) is taken as
+    empty, as for the exact inverses; a unit with small but normal diagonals is kept."""
+    w = mlp.init_weights(5)
+    blocks = random_blocks(6, 8)
+    blocks[3] = [1e-41, 0.0, 0.0, 0.0, 2e-41]   # D^-1/2 ~ 1e20: entries ~ 1e40
+    blocks[4] = [1e-30, 0.0, 0.0, 0.0, 1e-30]   # entries ~ 1e30: in range
+    feat = np.random.default_rng(2).normal(size=(6, 12))
+    M = mlp.minv(w, feat, blocks)
+    assert np.all(M[3] == 0)
+    assert np.all(np.isfinite(M)) and np.abs(M).max() <= np.finfo(np.float32).max
+    assert np.abs(M[4]).max() > 1e28
