@@ -194,10 +194,8 @@ int32_t perf_apply_JtJ(perf_scene* s, const void* d_x, const float* d_v, float* 
  * d_blocks  [units][5] FP32 (d, e_r, e_g, e_b, f): the unit's 4x4 block of J^T J is
  *           [[d I3, e], [e^T, f]], with each ray's partials aggregated over all of its
  *           samples before squaring (exact).  May be NULL.
- * kind      PERF_PRECOND_JACOBI: d_out [P] = 1/diag(J^T J) (0 where the diagonal is 0);
- *           PERF_PRECOND_BLOCK4: d_out [units][10] = upper triangle (00,01,02,03,11,12,13,22,23,33)
- *           of the inverse of each block after a ridge of 1e-6 max(d, f) (0 for empty units);
- *           inverses beyond the FP32 range are taken as 0 (perf_invert_blocks);
+ * kind      the preconditioner M^-1 in scaled form (see perf_invert_blocks): with
+ *           PERF_PRECOND_JACOBI d_out [units][4], with PERF_PRECOND_BLOCK4 d_out [units][8];
  *           PERF_PRECOND_NONE: d_out ignored.
  * d_F       device double[1], may be NULL.
  */
@@ -254,13 +252,21 @@ int32_t perf_upsample(const perf_scene_desc* from, const float* d_from, const pe
 int32_t perf_atomic_probe(float* d_y, int64_t n, int32_t reps, int32_t stride, void* stream);
 
 /*
- * Preconditioner inverse from given blocks (Sec. III-G), the step perf_build_precond ends with.
+ * Preconditioner from given blocks (Sec. III-G), the step perf_build_precond ends with, in the
+ * scaled form every PCG kernel applies.  No stored value depends on the scale of the block
+ * beyond its inverse square root, so the form stays in FP32 range for any block, including
+ * diagonals in the FP32 subnormal range (units seen only through near-opaque matter), and the
+ * unscaled inverse is never formed.
  * d_blocks  device float [units][5] = (d, e_r, e_g, e_b, f) of [[d I3, e], [e^T, f]].
- * kind      PERF_PRECOND_JACOBI: d_out [units][4] = (1/d, 1/d, 1/d, 1/f), 0 for a zero diagonal;
- *           PERF_PRECOND_BLOCK4: d_out [units][10] = upper triangle (00,01,02,03,11,12,13,22,23,33)
- *           of the inverse after a ridge of 1e-6 max(d, f), 0 for an empty unit.
- *           An inverse entry beyond the FP32 range (a diagonal in the subnormal range) makes the
- *           entry (Jacobi) or the unit (block) 0, as for an empty one.
+ * kind      PERF_PRECOND_JACOBI: d_out [units][4] = (t_d, t_d, t_d, t_f), t = 1/sqrt(diagonal),
+ *           0 for a zero diagonal; M^-1 = diag(t)^2 = 1/diag(J^T J).
+ *           PERF_PRECOND_BLOCK4: d_out [units][8] = (t_d, t_f, e~_r, e~_g, e~_b, 1/s, 0, 0): after a
+ *           ridge rho = 1e-6 max(d, f), t_d = (d + rho)^-1/2, t_f = (f + rho)^-1/2, the normalised
+ *           block D^-1/2 (B + rho I) D^-1/2 = [[I3, e~], [e~^T, 1]] with e~ = t_d t_f e, and s =
+ *           1 - |e~|^2 its Schur complement; M^-1 = (B + rho I)^-1 = D^-1/2 [[I3, e~], [e~^T, 1]]^-1
+ *           D^-1/2, applied by elimination (z_sigma = (y_sigma - e~ . y_c) / s, z_c = y_c -
+ *           e~ z_sigma on y = D^-1/2 r), which keeps FP32 rounding along the block's near-null
+ *           direction; all 8 are 0 for an empty unit (max(d, f) = 0).
  * Caller-owned device memory; asynchronous on stream.  PERF_EINVAL for a null pointer with
  * units > 0, units < 0 or another kind.
  */
@@ -281,9 +287,11 @@ int32_t perf_pack_bf16(const float* d_in, uint16_t* d_out, int64_t n, void* stre
  * perf_mlp_set_weights: d_w device bfloat16 weights in the packed order W1[64][16] b1[64]
  *   W2[64][64] b2[64] W3[16][64] b3[16] (inputs padded 12 -> 16, outputs 10 -> 16 with zeros);
  *   n_w must equal PERF_MLP_NW.  Copied into the workspace (requires desc.learned = 1).
- * perf_mlp_infer: d_minv [units][10] from features and blocks: the network's output is a
- *   lower-triangular L (10 values, softplus on the diagonal); M^-1 = D^-1/2 L L^T D^-1/2 with
- *   D = diag(d, d, d, f); units with max(d, f) = 0 get 0.
+ * perf_mlp_infer: d_minv [units][12] = (t_d, t_f, L00, L10, L11, L20, L21, L22, L30, L31, L32,
+ *   L33) from features and blocks: the network's output is a lower-triangular L (softplus on
+ *   the diagonal); M^-1 = D^-1/2 L L^T D^-1/2 with D^-1/2 = diag(t_d, t_d, t_d, t_f) as in
+ *   perf_invert_blocks (after the ridge), applied as D^-1/2 L (L^T (D^-1/2 r)); units with
+ *   max(d, f) = 0 get 0.
  * perf_mlp_train_step: one Adam step on a batch of n (feature, block) rows: per-unit error
  *   E = L L^T (Bn + damp I) - I with Bn = D^-1/2 B D^-1/2, so that the target is the damped
  *   normalised inverse (damp = 0: exact block-Jacobi; damp -> inf: Jacobi); the loss is the

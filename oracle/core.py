@@ -290,20 +290,12 @@ def jacobi_diag(blocks: np.ndarray) -> np.ndarray:
     return np.stack([b[:, 0], b[:, 0], b[:, 0], b[:, 4]], axis=1).reshape(-1)
 
 
-# Largest finite FP32 value.  The GPU path stores preconditioner inverses in FP32; an entry
-# beyond this range (a diagonal in the subnormal range, from a unit seen only through
-# near-opaque matter) is taken there as an empty unit's 0, and the oracle takes the same
-# reading so that both apply the same preconditioner.
-FP32_MAX = float(np.finfo(np.float32).max)
-
-
 def jacobi_inverse(blocks: np.ndarray) -> np.ndarray:
-    """M^{-1} = 1/diag(J^T J), 0 where the diagonal is 0 or its inverse exceeds FP32_MAX."""
+    """M^{-1} = 1/diag(J^T J) per parameter (Sec. III-G), 0 where the diagonal is 0."""
     d = jacobi_diag(blocks)
     out = np.zeros_like(d)
     nz = d > 0
     out[nz] = 1.0 / d[nz]
-    out[out > FP32_MAX] = 0.0
     return out
 
 
@@ -324,8 +316,7 @@ RIDGE = 1e-6
 
 
 def block_inverse(blocks: np.ndarray, ridge: float = RIDGE) -> np.ndarray:
-    """Inverse of each 4x4 block after adding ridge*max(d, f) to the diagonal; 0 for empty units
-    and for units with an entry beyond FP32_MAX.
+    """Inverse of each 4x4 block after adding ridge*max(d, f) to the diagonal; 0 for empty units.
 
     Returned as [units,4,4] (the plain matrix inverse, numpy.linalg.inv).
     """
@@ -337,7 +328,6 @@ def block_inverse(blocks: np.ndarray, ridge: float = RIDGE) -> np.ndarray:
     if np.any(live):
         Bl = B[live] + (ridge * m[live])[:, None, None] * np.eye(4)[None]
         out[live] = np.linalg.inv(Bl)
-    out[np.abs(out).max(axis=(1, 2)) > FP32_MAX] = 0.0  # beyond FP32: as an empty unit
     return out
 
 

@@ -148,15 +148,13 @@ def normalised_block(blocks: np.ndarray):
 
 
 def minv(w: np.ndarray, feat: np.ndarray, blocks: np.ndarray, emulate_bf16: bool = False) -> np.ndarray:
-    """[n, 4, 4] M^-1 = D^-1/2 L L^T D^-1/2 (zero for units with no rays, and for units with an
-    entry beyond the FP32 range, as the exact inverses)."""
+    """[n, 4, 4] M^-1 = D^-1/2 L L^T D^-1/2 (zero for units with no rays)."""
     raw, _ = forward(w, feat, emulate_bf16)
     L = factor(raw)
     _, dis, live = normalised_block(blocks)
     P = L @ np.transpose(L, (0, 2, 1))
     M = dis[:, :, None] * P * dis[:, None, :]
     M[~live] = 0.0
-    M[np.abs(M).max(axis=(1, 2)) > np.finfo(np.float32).max] = 0.0  # beyond FP32: as an empty unit
     return M
 
 

@@ -149,7 +149,7 @@ Layout make_layout(const perf_scene_desc& d, int n_cams) {
     L.vdelta = take(sizeof(float) * (size_t)P);
     L.vxt = take(sizeof(float) * (size_t)P);
     L.blocks = take(sizeof(float) * 5 * (size_t)units);
-    L.minv = take(sizeof(float) * (size_t)(10 * units > P ? 10 * units : P));
+    L.minv = take(sizeof(float) * 12 * (size_t)units);  // the largest scaled form (learned: 12 per unit)
     L.xb16 = d.param_dtype == PERF_BF16 ? take(sizeof(uint16_t) * (size_t)P) : 0;
     if (d.learned) {
         L.feat = take(sizeof(float) * 12 * (size_t)units);
@@ -548,7 +548,6 @@ int32_t perf_gn_step(perf_scene* s, float* d_x, const perf_pcg_opts* opts, perf_
     } else if (kind == PERF_PRECOND_LEARNED) {
         rc = learned_minv(s, xg, d_x);
         if (rc != PERF_OK) return rc;
-        apply_kind = PERF_PRECOND_BLOCK4;
     }
     CK(hipEventRecord(ev[2], st));
     // 3. PCG (Alg. 2) from Delta_0 = 0 with every scalar on the device

@@ -13,7 +13,6 @@
 // B[4(l/32)+j][l%32], j < 4; result register v of lane l is C[8(v/4)+4(l/32)+v%4][l%32].
 #include "perf_internal.h"
 
-#include <cfloat>
 #include <math.h>
 
 namespace perf {
@@ -212,37 +211,23 @@ __global__ __launch_bounds__(64 * kInferWaves) void k_mlp_infer(const unsigned s
         forward_tile(W, Xs, H1s, H2s, Os, nullptr, nullptr);
         if (unit < units) {
             const float* b = blocks + 5 * unit;
-            float* o = minv + 10 * unit;
+            float4* o = reinterpret_cast<float4*>(minv) + 3 * unit;
             const float d = b[0], f = b[4];
             const float m = fmaxf(d, f);
             if (!(m > 0.0f)) {
-#pragma unroll
-                for (int i = 0; i < 10; ++i) o[i] = 0.0f;
+                o[0] = o[1] = o[2] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
             } else {
                 float raw[NO];
 #pragma unroll
                 for (int i = 0; i < NO; ++i) raw[i] = Os[l * 17 + i];
                 float L[4][4];
                 make_L(raw, L);
-                const float rho = kRidge * m;
-                const float sd = 1.0f / sqrtf(d + rho), sf = 1.0f / sqrtf(f + rho);
-                const float ds[4] = {sd, sd, sd, sf};
-                float ov[10];
-                bool fits = true;
-                int k = 0;
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-#pragma unroll
-                    for (int j = i; j < 4; ++j, ++k) {
-                        float p = 0.0f;
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) p += L[i][q] * L[j][q];
-                        ov[k] = ds[i] * ds[j] * p;
-                        fits &= fabsf(ov[k]) <= FLT_MAX;
-                    }
-                // a unit whose inverse does not fit FP32 is taken as empty, as for the exact inverses
-#pragma unroll
-                for (int i = 0; i < 10; ++i) o[i] = fits ? ov[i] : 0.0f;
+                // scaled form: D^-1/2 (in double: d may be subnormal) and the factor L, row by row
+                const double rho = (double)kRidge * m;
+                const float td = (float)(1.0 / sqrt((double)d + rho)), tf = (float)(1.0 / sqrt((double)f + rho));
+                o[0] = make_float4(td, tf, L[0][0], L[1][0]);
+                o[1] = make_float4(L[1][1], L[2][0], L[2][1], L[2][2]);
+                o[2] = make_float4(L[3][0], L[3][1], L[3][2], L[3][3]);
             }
         }
     }

@@ -60,6 +60,9 @@ struct Ray {
     bool hit;
     unsigned jkey;  // the ray's jittering key (when jittering is on)
     float g0[3], gd[3];
+    const DevCam* cam;  // the camera (uniform over a workgroup)
+    int px, py;         // the pixel
+    float ox, oy;       // the ray's point inside the pixel (0.5, 0.5 at the centre)
 };
 
 // Jittering (Sec. IV): uniform numbers in [0, 1) from a counter-based generator, the 32-bit
@@ -86,6 +89,11 @@ __device__ __forceinline__ void make_ray(const Geo& G, const DevCam& c, int px, 
         ox = jitter_u(r.jkey, 0u);
         oy = jitter_u(r.jkey, 1u);
     }
+    r.cam = &c;
+    r.px = px;
+    r.py = py;
+    r.ox = ox;
+    r.oy = oy;
     const float dcx = ((float)px + ox - c.cx) / c.fx;
     const float dcy = ((float)py + oy - c.cy) / c.fy;
     float d0 = c.R[0] * dcx + c.R[1] * dcy + c.R[2];
@@ -190,32 +198,44 @@ struct Tex {
     float w[4];
 };
 
-// Far intersection with layer l beyond tmin and its bilinear equirectangular texels.
+// Far intersection with layer l beyond tmin and its bilinear equirectangular texels.  In double
+// precision from the camera and the pixel: a texel coordinate is an angle times W / 2 pi texels
+// per radian, so single precision (a rounded ray direction, then u near W) would move the
+// bilinear weights by about W * 1e-7.  A few of these per ray cost little beside the march.
 __device__ __forceinline__ bool env_hit(const Geo& G, const Ray& r, int l, float tmin, Tex& tx) {
     // the layer's radius by selects: a computed index into the kernel-argument struct would
     // move the whole struct to scratch memory
-    float R = G.radius[0];
+    float Rf = G.radius[0];
 #pragma unroll
-    for (int q = 1; q < kMaxLayers; ++q) R = (l == q) ? G.radius[q] : R;
-    const float b = r.o[0] * r.d[0] + r.o[1] * r.d[1] + r.o[2] * r.d[2];
-    const float cc = r.o[0] * r.o[0] + r.o[1] * r.o[1] + r.o[2] * r.o[2] - R * R;
-    const float disc = b * b - cc;
-    if (disc < 0.0f) return false;
-    const float t = -b + sqrtf(disc);
-    if (!(t > tmin)) return false;
-    const float px = r.o[0] + t * r.d[0], py = r.o[1] + t * r.d[1], pz = r.o[2] + t * r.d[2];
-    const float kInv2Pi = 0.15915494309189535f, kInvPi = 0.3183098861837907f;
+    for (int q = 1; q < kMaxLayers; ++q) Rf = (l == q) ? G.radius[q] : Rf;
+    const DevCam& c = *r.cam;
+    const double dcx = ((double)r.px + (double)r.ox - (double)c.cx) / (double)c.fx;
+    const double dcy = ((double)r.py + (double)r.oy - (double)c.cy) / (double)c.fy;
+    const double D0 = (double)c.R[0] * dcx + (double)c.R[1] * dcy + (double)c.R[2];
+    const double D1 = (double)c.R[3] * dcx + (double)c.R[4] * dcy + (double)c.R[5];
+    const double D2 = (double)c.R[6] * dcx + (double)c.R[7] * dcy + (double)c.R[8];
+    const double o0 = c.o[0], o1 = c.o[1], o2 = c.o[2], R = Rf;
+    // |o + s D| = R with D unnormalised: a s^2 + 2 b s + cc = 0, far root; t = s |D|
+    const double a = D0 * D0 + D1 * D1 + D2 * D2;
+    const double b = o0 * D0 + o1 * D1 + o2 * D2;
+    const double cc = o0 * o0 + o1 * o1 + o2 * o2 - R * R;
+    const double disc = b * b - a * cc;
+    if (disc < 0.0) return false;
+    const double sroot = (-b + sqrt(disc)) / a;
+    if (!(sroot * sqrt(a) > (double)tmin)) return false;
+    const double px = o0 + sroot * D0, py = o1 + sroot * D1, pz = o2 + sroot * D2;
+    const double kInv2Pi = 0.15915494309189535, kInvPi = 0.3183098861837907;
     const int W = G.env_w, Hh = G.env_h;
-    const float u = (atan2f(py, px) * kInv2Pi + 0.5f) * (float)W - 0.5f;
-    const float v = atan2f(sqrtf(px * px + py * py), pz) * kInvPi * (float)Hh - 0.5f;
-    const float fu0 = floorf(u);
-    const float fu = u - fu0;
+    const double u = (atan2(py, px) * kInv2Pi + 0.5) * (double)W - 0.5;
+    const double v = atan2(sqrt(px * px + py * py), pz) * kInvPi * (double)Hh - 0.5;
+    const double fu0 = floor(u);
+    const float fu = (float)(u - fu0);
     int i0 = (int)fu0;
     i0 = ((i0 % W) + W) % W;
     const int i1 = (i0 + 1 == W) ? 0 : i0 + 1;
-    const float vc = fminf(fmaxf(v, 0.0f), (float)(Hh - 1));
+    const double vc = fmin(fmax(v, 0.0), (double)(Hh - 1));
     const int j0 = min((int)vc, Hh - 2);
-    const float fv = vc - (float)j0;
+    const float fv = (float)(vc - (double)j0);
     const int base = G.nvox + l * W * Hh + j0 * W;
     tx.t[0] = base + i0;
     tx.t[1] = base + i1;

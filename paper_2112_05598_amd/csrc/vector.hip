@@ -8,7 +8,6 @@
 // of the solve checks, so the host can enqueue a whole solve without reading anything back.
 #include "perf_internal.h"
 
-#include <cfloat>
 #include <math.h>
 
 namespace perf {
@@ -63,20 +62,45 @@ __device__ __forceinline__ double dot4(float4 a, float4 b) {
     return (double)a.x * b.x + (double)a.y * b.y + (double)a.z * b.z + (double)a.w * b.w;
 }
 
-// z = M^-1 r for one unit.
+// z = M^-1 r for one unit, from the preconditioner in scaled form.  Every stored value stays in
+// FP32 range whatever the scale of the block (t = D^-1/2 is at most the inverse square root of
+// the smallest subnormal), and the unscaled inverse is never formed.
+//   Jacobi   t per parameter: z = t (t r).
+//   Block    (t_d, t_f, e~, 1/s): D^-1/2 = diag(t_d, t_d, t_d, t_f), the normalised block
+//            [[I, e~], [e~^T, 1]] and its Schur complement s = 1 - |e~|^2; with y = D^-1/2 r the
+//            block is solved by elimination, z_sigma = (y_sigma - e~ . y_c) / s,
+//            z_c = y_c - e~ z_sigma, then z = D^-1/2 z.  Elimination keeps the FP32 rounding
+//            error along the block's own near-null direction; multiplying by the explicit
+//            inverse, whose entries reach 1/s, would spread it over every direction.
+//   Learned  (t_d, t_f, L row by row): z = D^-1/2 L (L^T (D^-1/2 r)).
 template <int KIND>
 __device__ __forceinline__ float4 precond_apply(const float* __restrict__ minv, int64_t u, float4 r) {
     if constexpr (KIND == PERF_PRECOND_NONE) {
         return r;
     } else if constexpr (KIND == PERF_PRECOND_JACOBI) {
-        const float4 m = reinterpret_cast<const float4*>(minv)[u];
-        return make_float4(m.x * r.x, m.y * r.y, m.z * r.z, m.w * r.w);
+        const float4 t = reinterpret_cast<const float4*>(minv)[u];
+        return make_float4(t.x * (t.x * r.x), t.y * (t.y * r.y), t.z * (t.z * r.z), t.w * (t.w * r.w));
+    } else if constexpr (KIND == PERF_PRECOND_BLOCK4) {
+        const float4* q = reinterpret_cast<const float4*>(minv) + 2 * u;
+        const float4 q0 = q[0], q1 = q[1];
+        const float td = q0.x, tf = q0.y, e0 = q0.z, e1 = q0.w, e2 = q1.x, is = q1.y;
+        const float y0 = td * r.x, y1 = td * r.y, y2 = td * r.z, y3 = tf * r.w;
+        const float zs = (y3 - (e0 * y0 + e1 * y1 + e2 * y2)) * is;
+        return make_float4(td * (y0 - e0 * zs), td * (y1 - e1 * zs), td * (y2 - e2 * zs), tf * zs);
     } else {
-        const float* b = minv + 10 * u;
-        const float b00 = b[0], b01 = b[1], b02 = b[2], b03 = b[3], b11 = b[4], b12 = b[5], b13 = b[6], b22 = b[7],
-                    b23 = b[8], b33 = b[9];
-        return make_float4(b00 * r.x + b01 * r.y + b02 * r.z + b03 * r.w, b01 * r.x + b11 * r.y + b12 * r.z + b13 * r.w,
-                           b02 * r.x + b12 * r.y + b22 * r.z + b23 * r.w, b03 * r.x + b13 * r.y + b23 * r.z + b33 * r.w);
+        const float4* q = reinterpret_cast<const float4*>(minv) + 3 * u;
+        const float4 q0 = q[0], q1 = q[1], q2 = q[2];
+        const float td = q0.x, tf = q0.y;
+        const float l00 = q0.z, l10 = q0.w, l11 = q1.x, l20 = q1.y, l21 = q1.z, l22 = q1.w, l30 = q2.x, l31 = q2.y,
+                    l32 = q2.z, l33 = q2.w;
+        const float y0 = td * r.x, y1 = td * r.y, y2 = td * r.z, y3 = tf * r.w;
+        // w = L^T y, then v = L w
+        const float w0 = l00 * y0 + l10 * y1 + l20 * y2 + l30 * y3;
+        const float w1 = l11 * y1 + l21 * y2 + l31 * y3;
+        const float w2 = l22 * y2 + l32 * y3;
+        const float w3 = l33 * y3;
+        return make_float4(td * (l00 * w0), td * (l10 * w0 + l11 * w1), td * (l20 * w0 + l21 * w1 + l22 * w2),
+                           tf * (l30 * w0 + l31 * w1 + l32 * w2 + l33 * w3));
     }
 }
 
@@ -96,38 +120,32 @@ __global__ void k_sum_partials(const double* p, int64_t n, double scale, double*
     if (threadIdx.x == 0) *out = scale * s;
 }
 
-// Jacobi: 1/diag; block: closed-form inverse of [[d I, e], [e^T, f]] after a ridge.
+// Scaled form of the preconditioner (Sec. III-G) from the blocks [[d I, e], [e^T, f]], FP64 inside.
+// Jacobi: (t_d, t_d, t_d, t_f) with t = 1/sqrt(diagonal), 0 for a zero diagonal, so that
+// M^-1 = t^2 = 1/diag(J^T J).  Block: after a ridge rho = 1e-6 max(d, f), t_d = (d + rho)^-1/2,
+// t_f = (f + rho)^-1/2, the normalised coupling e~ = t_d t_f e and 1/s with s = 1 - |e~|^2, the
+// Schur complement of the normalised block [[I, e~], [e~^T, 1]]: (t_d, t_f, e~, 1/s, 0, 0).
 __global__ void k_invert(int kind, const float* __restrict__ blocks, int64_t units, float* __restrict__ out) {
     for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < units; u += (int64_t)gridDim.x * blockDim.x) {
         const float* b = blocks + 5 * u;
         const double d = b[0], e0 = b[1], e1 = b[2], e2 = b[3], f = b[4];
         if (kind == PERF_PRECOND_JACOBI) {
-            // an inverse that does not fit FP32 (a diagonal in the subnormal range, from a unit
-            // seen only through near-opaque matter) is taken as 0 like an empty diagonal
-            const double rd = 1.0 / d, rf = 1.0 / f;
-            const float id = (d > 0.0 && rd <= (double)FLT_MAX) ? (float)rd : 0.0f;
-            const float iff = (f > 0.0 && rf <= (double)FLT_MAX) ? (float)rf : 0.0f;
-            reinterpret_cast<float4*>(out)[u] = make_float4(id, id, id, iff);
+            const float td = d > 0.0 ? (float)(1.0 / sqrt(d)) : 0.0f;
+            const float tf = f > 0.0 ? (float)(1.0 / sqrt(f)) : 0.0f;
+            reinterpret_cast<float4*>(out)[u] = make_float4(td, td, td, tf);
         } else {
-            float* o = out + 10 * u;
+            float4* o = reinterpret_cast<float4*>(out) + 2 * u;
             const double m = fmax(d, f);
             if (!(m > 0.0)) {
-#pragma unroll
-                for (int i = 0; i < 10; ++i) o[i] = 0.0f;
+                o[0] = o[1] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
                 continue;
             }
             const double rho = 1e-6 * m;
-            const double dd = d + rho, ff = f + rho;
-            const double s = ff - (e0 * e0 + e1 * e1 + e2 * e2) / dd;  // Schur complement of d I
-            const double id = 1.0 / dd, is = 1.0 / s, k = id * id * is;
-            const double v[10] = {id + e0 * e0 * k, e0 * e1 * k,      e0 * e2 * k, -e0 * id * is, id + e1 * e1 * k,
-                                  e1 * e2 * k,      -e1 * id * is,    id + e2 * e2 * k, -e2 * id * is, is};
-            // a unit whose inverse does not fit FP32 is taken as empty (as for the Jacobi case)
-            bool fits = true;
-#pragma unroll
-            for (int i = 0; i < 10; ++i) fits &= fabs(v[i]) <= (double)FLT_MAX;
-#pragma unroll
-            for (int i = 0; i < 10; ++i) o[i] = fits ? (float)v[i] : 0.0f;
+            const double td = 1.0 / sqrt(d + rho), tf = 1.0 / sqrt(f + rho);
+            const double a0 = e0 * td * tf, a1 = e1 * td * tf, a2 = e2 * td * tf;
+            const double is = 1.0 / (1.0 - (a0 * a0 + a1 * a1 + a2 * a2));
+            o[0] = make_float4((float)td, (float)tf, (float)a0, (float)a1);
+            o[1] = make_float4((float)a2, (float)is, 0.0f, 0.0f);
         }
     }
 }
@@ -410,9 +428,13 @@ hipError_t launch_pcg_init(int kind, const float* b, const float* minv, float* r
             hipLaunchKernelGGL(k_pcg_init<PERF_PRECOND_JACOBI>, dim3(g), dim3(kVecBlock), 0, st, B, minv, R, Z, Pp, D,
                                units, partials);
             break;
-        default:
+        case PERF_PRECOND_BLOCK4:
             hipLaunchKernelGGL(k_pcg_init<PERF_PRECOND_BLOCK4>, dim3(g), dim3(kVecBlock), 0, st, B, minv, R, Z, Pp, D,
                                units, partials);
+            break;
+        default:
+            hipLaunchKernelGGL(k_pcg_init<PERF_PRECOND_LEARNED>, dim3(g), dim3(kVecBlock), 0, st, B, minv, R, Z, Pp,
+                               D, units, partials);
             break;
     }
     hipLaunchKernelGGL(k_pcg_init_fin, dim3(1), dim3(kVecBlock), 0, st, partials, (int64_t)g, scalars, iflags);
@@ -446,8 +468,12 @@ hipError_t launch_pcg_update(int kind, const float* minv, float* delta, float* r
             hipLaunchKernelGGL(k_pcg_update<PERF_PRECOND_JACOBI>, dim3(g), dim3(kVecBlock), 0, st, minv, D, R, Z, Pp,
                                A, units, partials, scalars, iflags);
             break;
-        default:
+        case PERF_PRECOND_BLOCK4:
             hipLaunchKernelGGL(k_pcg_update<PERF_PRECOND_BLOCK4>, dim3(g), dim3(kVecBlock), 0, st, minv, D, R, Z, Pp,
+                               A, units, partials, scalars, iflags);
+            break;
+        default:
+            hipLaunchKernelGGL(k_pcg_update<PERF_PRECOND_LEARNED>, dim3(g), dim3(kVecBlock), 0, st, minv, D, R, Z, Pp,
                                A, units, partials, scalars, iflags);
             break;
     }

@@ -164,7 +164,8 @@ class Scene:
         return y
 
     def build_precond(self, x, kind: str = "jacobi"):
-        """(grad = -J^T r [P], blocks [units,5], M^-1 ([P] Jacobi or [units,10] block), F)."""
+        """(grad = -J^T r [P], blocks [units,5], M^-1 in scaled form ([units,4] Jacobi D^-1/2 or
+        [units,8] block (t_d, t_f, e~, 1/s, 0, 0)), F)."""
         self._check_params(x)
         self._bind()
         k = _PRECOND[kind]
@@ -172,9 +173,9 @@ class Scene:
         blocks = torch.empty(self.n_units * 5, dtype=torch.float32, device=self.device)
         out = None
         if k == abi.PERF_PRECOND_JACOBI:
-            out = torch.empty(self.n_params, dtype=torch.float32, device=self.device)
+            out = torch.empty(self.n_units, 4, dtype=torch.float32, device=self.device)
         elif k == abi.PERF_PRECOND_BLOCK4:
-            out = torch.empty(self.n_units * 10, dtype=torch.float32, device=self.device)
+            out = torch.empty(self.n_units, 8, dtype=torch.float32, device=self.device)
         F = torch.zeros(1, dtype=torch.float64, device=self.device)
         abi.check(self.lib.perf_build_precond(self.handle, _ptr(x), k, _ptr(grad), _ptr(blocks), _ptr(out), _ptr(F)))
         return grad, blocks.view(-1, 5), out, F
@@ -211,12 +212,12 @@ class Scene:
         abi.check(self.lib.perf_mlp_set_weights(self.handle, _ptr(self._mlp_w), abi.PERF_MLP_NW))
 
     def mlp_infer(self, feat: torch.Tensor, blocks: torch.Tensor):
-        """[units, 10] upper triangles of the predicted block inverses."""
+        """[units, 12] predicted block inverses in scaled form (t_d, t_f, L row by row)."""
         self._bind()
-        out = torch.empty(self.n_units * 10, dtype=torch.float32, device=self.device)
+        out = torch.empty(self.n_units * 12, dtype=torch.float32, device=self.device)
         abi.check(self.lib.perf_mlp_infer(self.handle, _ptr(feat.contiguous()), _ptr(blocks.contiguous()),
                                           _ptr(out)))
-        return out.view(-1, 10)
+        return out.view(-1, 12)
 
     def gn_step(self, x: torch.Tensor, max_iters: int = 20, precond: str = "jacobi", rel_tol: float = 0.0,
                 abs_eps: float = 0.0, stall_ratio: float = 0.0, line_search: bool = True, ls_factor: float = 0.7,
@@ -266,14 +267,14 @@ def upsample(spec_from, x_from: torch.Tensor, spec_to, out: Optional[torch.Tenso
 
 
 def invert_blocks(blocks: torch.Tensor, kind: str = "jacobi", stream=None) -> torch.Tensor:
-    """Preconditioner inverse of given (d, e_r, e_g, e_b, f) blocks [units, 5] (perf_invert_blocks):
-    [units, 4] Jacobi entries or [units, 10] upper triangles of the ridged block inverses."""
+    """Preconditioner of given (d, e_r, e_g, e_b, f) blocks [units, 5] in scaled form
+    (perf_invert_blocks): [units, 4] Jacobi D^-1/2 or [units, 8] (t_d, t_f, e~, 1/s, 0, 0)."""
     lib = abi.load()
     if blocks.dtype != torch.float32 or not blocks.is_cuda or not blocks.is_contiguous() or blocks.dim() != 2 \
             or blocks.shape[1] != 5:
         raise ValueError("blocks must be a contiguous float32 device tensor of shape [units, 5]")
     k = _PRECOND[kind]
-    width = {abi.PERF_PRECOND_JACOBI: 4, abi.PERF_PRECOND_BLOCK4: 10}.get(k)
+    width = {abi.PERF_PRECOND_JACOBI: 4, abi.PERF_PRECOND_BLOCK4: 8}.get(k)
     if width is None:
         raise ValueError("kind must be 'jacobi' or 'block'")
     out = torch.empty(blocks.shape[0], width, dtype=torch.float32, device=blocks.device)

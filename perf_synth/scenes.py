@@ -21,6 +21,12 @@ from typing import List, Optional, Sequence, Tuple
 import numpy as np
 
 
+def _f32(v):
+    """The nearest single-precision values, kept as float64: the library reads scene and camera
+    parameters in single precision, so the generators hand every consumer exactly those values."""
+    return np.asarray(v, dtype=np.float64).astype(np.float32).astype(np.float64)
+
+
 @dataclasses.dataclass
 class SceneSpec:
     nx: int
@@ -33,6 +39,13 @@ class SceneSpec:
     env_h: int = 32
     step_vox: float = 0.5
     background: Tuple[float, float, float] = (0.0, 0.0, 0.0)
+
+    def __post_init__(self):
+        self.bbox_min = tuple(float(v) for v in _f32(self.bbox_min))
+        self.bbox_max = tuple(float(v) for v in _f32(self.bbox_max))
+        self.layer_radii = tuple(float(v) for v in _f32(self.layer_radii))
+        self.step_vox = float(_f32(self.step_vox))
+        self.background = tuple(float(v) for v in _f32(self.background))
 
     @property
     def n_layers(self) -> int:
@@ -73,6 +86,11 @@ class Cameras:
     cy: np.ndarray
     width: int
     height: int
+
+    def __post_init__(self):
+        self.origin = _f32(self.origin)
+        self.rot = _f32(self.rot)
+        self.fx, self.fy, self.cx, self.cy = _f32(self.fx), _f32(self.fy), _f32(self.cx), _f32(self.cy)
 
     @property
     def n(self) -> int:

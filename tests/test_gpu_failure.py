@@ -80,4 +80,4 @@ def test_untouched_units_get_zero_inverse():
     dead = (d == 0) & (f == 0)
     assert dead.any() and (~dead).any()
     assert np.all(minv.view(-1, 4).cpu().numpy()[dead] == 0)
-    assert np.all(binv.view(-1, 10).cpu().numpy()[dead] == 0)
+    assert np.all(binv.view(-1, 8).cpu().numpy()[dead] == 0)

@@ -70,9 +70,14 @@ def test_mlp_inference_matches_fp64_mlp(setup):
     f64, b64 = feat.cpu().numpy().astype(np.float64), blocks.cpu().numpy().astype(np.float64)
     iu = np.triu_indices(4)
     _, dis, live = mlp.normalised_block(b64)
-    # compare normalised inverses D^1/2 M^-1 D^1/2 = L L^T (order one entries)
+    # the scaled form: D^-1/2 (t_d, t_f) and the factor L; compare the normalised inverses
+    # L L^T = D^1/2 M^-1 D^1/2 (order-one entries)
+    from gpu_checks import learned_factor
+    np.testing.assert_allclose(out[live, 0], dis[live, 0], rtol=1e-6)
+    np.testing.assert_allclose(out[live, 1], dis[live, 3], rtol=1e-6)
+    L = learned_factor(out)
+    got = (L @ np.transpose(L, (0, 2, 1)))[:, iu[0], iu[1]]
     scale = np.where(live[:, None], 1.0 / (dis[:, iu[0]] * dis[:, iu[1]] + 1e-300), 0.0)
-    got = out * scale
     emu = mlp.minv(wq, f64, b64, emulate_bf16=True)[:, iu[0], iu[1]] * scale
     exact = mlp.minv(wq, f64, b64)[:, iu[0], iu[1]] * scale
     # same bf16 roundings of inputs and activations: FP32 accumulation and rare ties only
@@ -80,11 +85,8 @@ def test_mlp_inference_matches_fp64_mlp(setup):
     # against the all-FP64 network: three bf16 roundings (unit roundoff 2^-9) per path
     assert rel(got[live], exact[live]) <= 3e-2
     assert np.all(out[~live] == 0)
-    # every predicted block inverse is symmetric positive definite
-    M = np.zeros((live.sum(), 4, 4))
-    M[:, iu[0], iu[1]] = got[live]
-    M[:, iu[1], iu[0]] = got[live]
-    assert np.all(np.linalg.eigvalsh(M)[:, 0] > 0)
+    # the factor has a positive diagonal (softplus): every predicted inverse is SPD
+    assert np.all(L[live][:, [0, 1, 2, 3], [0, 1, 2, 3]] > 0)
 
 
 @pytest.mark.parametrize("damp", [0.0, 0.3])
@@ -119,12 +121,41 @@ def test_mlp_training_gradient(setup, damp):
     assert np.all(np.sign(moved[nz]) == -np.sign(g_or[nz]))
 
 
-def test_learned_gn_step(setup):
+def learned_weights(seed):
+    """A network away from its L = I start (bf16 bits and their FP64 values)."""
     from oracle import mlp
+    rng = np.random.default_rng(seed)
+    w64 = mlp.init_weights(seed) + 0.05 * rng.normal(size=mlp.NW)
+    p = mlp.unpack(w64); p["W1"][:, 12:] = 0; p["W3"][10:] = 0
+    bits = mlp.bf16_bits(mlp.pack(p))
+    return bits, mlp.bits_to_f64(bits)
+
+
+def test_learned_gn_step_matches_oracle(setup):
+    """One GN step with the learned preconditioner against the oracle's GN step (Eq. 7, Alg. 2,
+    Alg. 3) with M^-1 from the FP64 network on the same features: the network's bf16 activations
+    leave the per-unit inverse within the inference bound (2e-3) of the FP64 emulation, which the
+    PCG scalars inherit, so they get 1e-3 here; with the library's own inverse, multiplied out
+    in FP64, the solve itself matches to the J^T J v bound (1e-4)."""
+    import oracle
+    from oracle import mlp
+    from gpu_checks import learned_minv
+    from gpu_checks import check_pcg_history
     w, orc, sc, targets, t, x = setup
-    bits = mlp.bf16_bits(mlp.init_weights(0))
+    bits, wq = learned_weights(7)
     sc.mlp_set_weights(torch.from_numpy(bits.view(np.int16)).cuda().view(torch.bfloat16))
     tx = torch.from_numpy(x).cuda()
-    st = sc.gn_step(tx.clone(), max_iters=10, precond="learned")
+    feat, blocks = sc.features(tx)
+    minv_gpu = learned_minv(sc.mlp_infer(feat, blocks).cpu().numpy())
+    x64 = x.astype(np.float64)
+    _, b_or, _ = orc.grad_blocks(x64, targets)
+    minv_or = mlp.minv(wq, feat.cpu().numpy().astype(np.float64), b_or, emulate_bf16=True)
+    st = sc.gn_step(tx.clone(), max_iters=8, precond="learned")
     assert st["F_after"] < st["F_before"]
     assert st["pcg_iters"] >= 1 and not (st["flags"] & 1)
+    for minv, tol in ((minv_gpu, 1e-4), (minv_or, 1e-3)):
+        ref = oracle.gn_step(orc, x64, targets, precond="learned", max_iters=8, learned_minv=minv)
+        assert abs(st["F_before"] - ref["F_before"]) <= 1e-5 * ref["F_before"]
+        assert st["pcg_iters"] == ref["pcg"].iters
+        check_pcg_history(st, ref["pcg"], min(5, ref["pcg"].iters), tol=tol)
+        assert abs(st["F_after"] - ref["F_after"]) <= 1e-3 * ref["F_before"], (st["F_after"], ref["F_after"])

@@ -140,30 +140,35 @@ def test_jacobi_scaled_gradient(case):
     """M^-1 b per unit (what PCG starts from): each unit is rescaled by its own diagonal,
     so units seen only behind near-opaque matter must keep their relative precision."""
     import oracle
+    from gpu_checks import jacobi_minv
     grad, blocks, jac, _ = case.sc.build_precond(case.tx, "jacobi")
     g_or, b_or, _ = case.orc.grad_blocks(case.x64, case.targets)
     z_or = oracle.jacobi_inverse(b_or) * g_or
     if np.linalg.norm(z_or) == 0 or case.zero_residual:
         return
-    z = (jac * grad).cpu().numpy()
+    z = jacobi_minv(jac.cpu().numpy()) * grad.cpu().numpy().astype(np.float64)
     assert rel(z, z_or) <= 1e-3
 
 
 def test_preconditioner_inverses(case):
+    """The scaled forms, multiplied out in FP64, against the oracle's exact inverses (Sec. III-G)
+    of the same blocks (each call's own blocks: atomic summation order differs between calls,
+    and a near-singular block turns that rounding into a visible change of its inverse)."""
     import oracle
-    # the GPU inverses of the GPU blocks against the oracle's inverses of the same blocks
-    # (each call's own blocks: atomic summation order differs between calls, and a
-    # near-singular block turns that rounding into a visible change of its inverse)
+    from gpu_checks import block_minv, jacobi_minv
     _, blocks, jac, _ = case.sc.build_precond(case.tx, "jacobi")
     j_or = oracle.jacobi_inverse(blocks.cpu().numpy().astype(np.float64))
-    np.testing.assert_allclose(jac.cpu().numpy(), j_or, rtol=1e-6, atol=0)
+    np.testing.assert_allclose(jacobi_minv(jac.cpu().numpy()), j_or, rtol=3e-7, atol=0)
     _, blocks, binv, _ = case.sc.build_precond(case.tx, "block")
     Binv_or = oracle.block_inverse(blocks.cpu().numpy().astype(np.float64))
-    g = binv.cpu().numpy().reshape(-1, 10)
-    iu = np.triu_indices(4)
-    ref = Binv_or[:, iu[0], iu[1]]
-    scale = np.abs(ref).max(axis=1, keepdims=True) + 1e-30
-    assert np.abs((g - ref) / scale).max() <= 1e-3
+    g = block_minv(binv.cpu().numpy())
+    scale = np.abs(Binv_or).max(axis=(1, 2)) + 1e-300
+    live = scale > 1e-300
+    assert np.all(g[~live] == 0)
+    if live.any():  # (the zero start with a black background has no live unit)
+        err = np.abs(g - Binv_or).max(axis=(1, 2))[live] / scale[live]
+        print(f"[precond] block inverse max per-unit error {err.max():.3e}", flush=True)
+        assert err.max() <= 1e-5
 
 
 def test_footprint_counts(case):
@@ -178,27 +183,12 @@ def test_footprint_counts(case):
     assert int(t[1]) == int(L.sum()) and int(t[2]) == int((K > 0).sum())
 
 
-def check_pcg_history(st, pcg, n, tol=1e-4):
-    """PCG scalars of the first n iterations against the FP64 run.
-
-    The FP32 products and vectors leave an error of about tol * |r_0| in the residual
-    vector r_k (tol = the J^T J v bound), so R_k = |r_k|^2 carries an absolute error of
-    about 2 tol |r_k| |r_0|: relative 2 tol sqrt(R_0 / R_k), which grows as CG converges.
-    alpha_k and beta_k are ratios of such dot products and get the same scaled bound.
-    """
-    R0 = pcg.R0
-    for k in range(n):
-        Rk = pcg.R[k]
-        scale = 2 * tol * np.sqrt(R0 / Rk)
-        assert abs(st["R"][k] - Rk) <= scale * Rk, (k, st["R"][k], Rk)
-        assert abs(st["alpha"][k] - pcg.alpha[k]) <= scale * abs(pcg.alpha[k]), (k, st["alpha"][k], pcg.alpha[k])
-        if k < n - 1:
-            assert abs(st["beta"][k] - pcg.beta[k]) <= scale * abs(pcg.beta[k]), (k, st["beta"][k], pcg.beta[k])
-
-
 @pytest.mark.parametrize("precond", ["jacobi", "block", "none"])
 def test_gn_step_matches_oracle(case, precond):
+    """One GN step (Eq. 7, Alg. 2, Alg. 3) against the oracle's: PCG scalars alpha_k, beta_k of the
+    first five iterations within 1e-4, F after the line search within 1e-3 of F before."""
     import oracle
+    from gpu_checks import check_pcg_history
     if case.w.name == "ragged" and case.x.max() == 0 and precond != "jacobi":
         pytest.skip("one preconditioner suffices for the zero start")
     x = case.tx.clone()

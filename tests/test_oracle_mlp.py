@@ -149,15 +149,61 @@ def test_feature_sums_identities(oracle_mod):
     assert np.all(sums[:, 0] >= 0) and np.all(sums[:, 1] <= sums[:, 0] + 1e-12)
 
 
-def test_inverse_beyond_fp32_is_empty(mlp):
-    """A unit whose learned inverse would exceed the FP32 range (subnormal diagonals) is taken as
-    empty, as for the exact inverses; a unit with small but normal diagonals is kept."""
+def test_learned_inverse_scales_with_the_block(mlp):
+    """M^-1 = D^-1/2 L L^T D^-1/2 with B~ = D^-1/2 B D^-1/2 scale-free: scaling a block by s scales
+    the predicted inverse by 1/s exactly, at any s (no threshold on tiny diagonals)."""
     w = mlp.init_weights(5)
     blocks = random_blocks(6, 8)
-    blocks[3] = [1e-41, 0.0, 0.0, 0.0, 2e-41]   # D^-1/2 ~ 1e20: entries ~ 1e40
-    blocks[4] = [1e-30, 0.0, 0.0, 0.0, 1e-30]   # entries ~ 1e30: in range
     feat = np.random.default_rng(2).normal(size=(6, 12))
-    M = mlp.minv(w, feat, blocks)
-    assert np.all(M[3] == 0)
-    assert np.all(np.isfinite(M)) and np.abs(M).max() <= np.finfo(np.float32).max
-    assert np.abs(M[4]).max() > 1e28
+    M1 = mlp.minv(w, feat, blocks)
+    for s in (1e-20, 1e-41):
+        Ms = mlp.minv(w, feat, blocks * s)
+        np.testing.assert_allclose(Ms * s, M1, rtol=1e-12, atol=0)
+    # units no ray touches get 0; the others are symmetric positive definite
+    assert np.all(M1[:3] == 0)
+    assert np.all(np.linalg.eigvalsh(M1[3:]) > 0)
+
+
+def test_feature_sums_axis_ray_closed_form(oracle_mod):
+    """Every channel of the feature sums on a ray along -x through voxel centres of a uniform
+    medium, written out in closed form: samples at the step midpoints, trilinear weights
+    max(0, 1 - |g - i|) along x (clamped to the edge) and 1 on the centre voxel in y and z,
+    T_k = exp(-sigma delta k), alpha = 1 - exp(-sigma delta), G_k = sum_{m>k} T_m alpha c +
+    T_end S with S the layer seen in front of the background; for the layer's texels the
+    bilinear weights sum to 1, so the texel sums total (1, T_end, T_end bg, alpha_layer)."""
+    n, step = 8, 0.6
+    spec = ps.SceneSpec(n, n, n, layer_radii=(1.8,), env_w=16, env_h=8, step_vox=step,
+                        background=(0.3, 0.6, 0.05))
+    h = 2.0 / n
+    cams = ps.cameras_from_origins([[3.0, 0.0, 0.0]], 1, 1, 20.0)
+    cams.origin[0] = [3.0, -1 + 2.5 * h, -1 + 5.5 * h]
+    cams.rot[0] = np.array([[0.0, 0.0, -1.0], [1.0, 0.0, 0.0], [0.0, -1.0, 0.0]])
+    sigma, c0 = 0.35, np.array([0.2, 0.5, 0.9])
+    ce, ae = np.array([0.7, 0.1, 0.4]), 0.8
+    grid = np.zeros((n, n, n, 4)); grid[..., :3] = c0; grid[..., 3] = sigma
+    env = np.zeros((1, spec.env_h, spec.env_w, 4)); env[..., :3] = ce; env[..., 3] = ae
+    x = np.concatenate([grid.reshape(-1), env.reshape(-1)])
+    sc = oracle_mod.OracleScene(spec, cams)
+    sums = sc.feature_sums(x)
+    # closed form (the step as the scene holds it, a single-precision value)
+    step = spec.step_vox
+    L = 2.0 / h
+    K = int(np.ceil(L / step))
+    delta = np.minimum(step, L - step * np.arange(K))
+    s_mid = step * np.arange(K) + 0.5 * delta          # voxel lengths from the entry at x = +1
+    gx = np.clip(7.5 - s_mid, 0.0, n - 1.0)            # cell-centred grid coordinate along x
+    alpha = 1.0 - np.exp(-sigma * delta)
+    T = np.exp(-sigma * np.concatenate([[0.0], np.cumsum(delta)[:-1]]))
+    T_end = np.exp(-sigma * delta.sum())
+    S = ae * ce + (1 - ae) * np.array(spec.background)
+    G = np.array([(T[k + 1:] * alpha[k + 1:]).sum() * c0 + T_end * S for k in range(K)])
+    want = np.zeros((n, 6))
+    for i in range(n):
+        wgt = np.maximum(0.0, 1.0 - np.abs(gx - i))
+        want[i] = [wgt.sum(), (wgt * T).sum(), *(wgt[:, None] * G).sum(0), (wgt * alpha).sum()]
+    vox = sums[:spec.n_vox].reshape(n, n, n, 6)
+    np.testing.assert_allclose(vox[5, 2, :], want, rtol=1e-12, atol=1e-15)
+    mask = np.ones((n, n, n), bool); mask[5, 2, :] = False
+    assert np.all(vox[mask] == 0.0)
+    tex = sums[spec.n_vox:].sum(0)
+    np.testing.assert_allclose(tex, [1.0, T_end, *(T_end * np.array(spec.background)), ae], rtol=1e-12)

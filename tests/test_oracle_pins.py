@@ -172,9 +172,10 @@ def test_empty_grid_returns_env_colour(oracle_mod):
     H = sc.render(x)[0]
     for ray in range(49):
         o, d = sc.ray(ray)
-        # far intersection with the sphere of radius 1.8 by polynomial roots
-        t = max(np.roots([d @ d, 2 * o @ d, o @ o - 1.8 ** 2]).real)
-        q = (o + t * d) / 1.8
+        # far intersection with the layer sphere (radius 1.8 in single precision) by polynomial roots
+        R = spec.layer_radii[0]
+        t = max(np.roots([d @ d, 2 * o @ d, o @ o - R ** 2]).real)
+        q = (o + t * d) / R
         v = math.acos(q[2]) / math.pi * 16 - 0.5
         assert 0.0 <= v <= 15.0
         np.testing.assert_allclose(H[ray], [0.1 + 0.05 * v, 0.9 - 0.03 * v, 0.5], rtol=1e-12)
@@ -191,8 +192,9 @@ def test_env_azimuth_linear(oracle_mod):
     H = sc.render(x)[0]
     for ray in range(49):
         o, d = sc.ray(ray)
-        t = max(np.roots([d @ d, 2 * o @ d, o @ o - 1.8 ** 2]).real)
-        q = (o + t * d) / 1.8
+        R = spec.layer_radii[0]
+        t = max(np.roots([d @ d, 2 * o @ d, o @ o - R ** 2]).real)
+        q = (o + t * d) / R
         u = (math.atan2(q[1], q[0]) / (2 * math.pi) + 0.5) * 64 - 0.5
         if 0.0 <= u <= 63.0:  # away from the wrap seam
             assert math.isclose(H[ray][0], 0.01 * u, rel_tol=1e-11)
@@ -236,6 +238,25 @@ def test_partition_of_unity(oracle_mod):
     np.testing.assert_allclose(H, 1.0, atol=1e-12)
 
 
+def pinhole_chord(spec, cams, ray):
+    """Chord of a pixel ray through the grid box in shortest-voxel-side units, from the pinhole
+    model and a slab test written out here (0 for a miss)."""
+    per = cams.width * cams.height
+    cam, pix = divmod(int(ray), per)
+    py, px = divmod(pix, cams.width)
+    dc = np.array([(px + 0.5 - cams.cx[cam]) / cams.fx[cam], (py + 0.5 - cams.cy[cam]) / cams.fy[cam], 1.0])
+    d = np.asarray(cams.rot[cam]).reshape(3, 3) @ dc
+    d /= np.linalg.norm(d)
+    o = np.asarray(cams.origin[cam], dtype=np.float64)
+    lo, hi = np.asarray(spec.bbox_min), np.asarray(spec.bbox_max)
+    with np.errstate(divide="ignore"):
+        ta, tb = (lo - o) / d, (hi - o) / d
+    t0 = max(np.max(np.minimum(ta, tb)), 0.0)
+    t1 = np.min(np.maximum(ta, tb))
+    h = min((hi[a] - lo[a]) / n for a, n in enumerate((spec.nx, spec.ny, spec.nz)))
+    return max(t1 - t0, 0.0) / h
+
+
 def test_transmittance_bounds(oracle_mod, tiny):
     sc, spec, x, rays = tiny
     for ray in rays[:10]:
@@ -245,8 +266,26 @@ def test_transmittance_bounds(oracle_mod, tiny):
         assert np.all(np.diff(T) <= 1e-15)
         if len(s["T"]):
             assert s["T"][0] == 1.0
-            assert abs(s["delta"].sum() - s["delta"].sum()) == 0.0
+            # the steps add up to the chord (the last one shortened)
+            L = pinhole_chord(spec, sc.cams, ray)
+            assert abs(s["delta"].sum() - L) <= 1e-12 * max(L, 1.0), (s["delta"].sum(), L)
+            assert len(s["delta"]) == int(np.ceil(L / spec.step_vox - 1e-12))
             assert np.all(s["delta"] <= spec.step_vox + 1e-15) and np.all(s["delta"] > 0)
+
+
+def test_chord_pin_on_non_unit_steps(oracle_mod):
+    """Steps of 0.3 voxel on a non-cubic box: K = ceil(L / step) samples whose steps sum to L."""
+    w = ps.workload("small")
+    spec = dataclasses.replace(w.spec, step_vox=0.3)
+    sc = oracle_mod.OracleScene(spec, w.cams)
+    _, _, K = sc.footprint()
+    hit = np.nonzero(K > 0)[0]
+    x = random_x(spec, 2)
+    for ray in hit[:: max(len(hit) // 12, 1)]:
+        s = sc.ray_samples(x, ray)
+        L = pinhole_chord(spec, w.cams, ray)
+        assert abs(s["delta"].sum() - L) <= 1e-12 * max(L, 1.0)
+        assert len(s["delta"]) == K[ray]
 
 
 def test_axis_ray_footprint(oracle_mod):
@@ -386,26 +425,28 @@ def test_block_inverse_is_inverse(oracle_mod):
     np.testing.assert_allclose(jac[20:24], [1 / d[5]] * 3 + [1 / f[5]])
 
 
-def test_inverses_beyond_fp32_are_empty(oracle_mod):
-    """A diagonal in the FP32 subnormal range has an inverse beyond the FP32 range: the unit (block)
-    or the entry (Jacobi) is then 0, as an empty one; a small normal diagonal is inverted."""
-    fmax = float(np.finfo(np.float32).max)
-    blocks = np.array([[1e-40, 0.0, 0.0, 0.0, 2.0],    # tiny d, normal f
-                       [1e-30, 0.0, 0.0, 0.0, 1e-30],  # small but invertible
-                       [1e-41, 1e-42, 0.0, 0.0, 1e-41],
-                       [2.0, 0.5, 0.0, 0.0, 1.0]])
-    jac = oracle_mod.jacobi_inverse(blocks).reshape(-1, 4)
-    assert np.all(jac[0, :3] == 0) and jac[0, 3] == 0.5
-    np.testing.assert_allclose(jac[1], 1e30, rtol=1e-12)
-    assert np.all(jac[2] == 0)
-    np.testing.assert_allclose(jac[3], [0.5, 0.5, 0.5, 1.0])
-    binv = oracle_mod.block_inverse(blocks)
-    assert np.all(binv[2] == 0)  # both diagonals subnormal: the ridge cannot lift them into range
-    assert np.all(np.abs(binv) <= fmax)
-    B = oracle_mod.block_matrix(blocks)
-    for i in (0, 1, 3):  # unit 0: the ridge 1e-6 max(d, f) keeps the inverse in range
-        m = max(blocks[i, 0], blocks[i, 4])
-        np.testing.assert_allclose((B[i] + 1e-6 * m * np.eye(4)) @ binv[i], np.eye(4), atol=1e-9)
+def test_inverses_of_tiny_diagonals_are_exact(oracle_mod):
+    """The inverses are the exact ones at any scale (Sec. III-G: M = diag(J^T J)): a block scaled
+    by s has its inverse scaled by 1/s, down to diagonals of 1e-44 (units seen only through
+    near-opaque matter), with no threshold anywhere."""
+    base = np.array([[2.0, 0.3, -0.2, 0.1, 1.5],
+                     [1.0, 0.0, 0.0, 0.0, 4.0],
+                     [0.7, 0.5, 0.1, -0.4, 0.9]])
+    B = oracle_mod.block_matrix(base)
+    for scale in (1.0, 1e-30, 1e-40, 1e-44):
+        blocks = base * scale
+        jac = oracle_mod.jacobi_inverse(blocks).reshape(-1, 4)
+        np.testing.assert_allclose(jac[:, 0], 1.0 / (scale * base[:, 0]), rtol=1e-14)
+        np.testing.assert_allclose(jac[:, 3], 1.0 / (scale * base[:, 4]), rtol=1e-14)
+        binv = oracle_mod.block_inverse(blocks)
+        for i in range(3):
+            m = max(base[i, 0], base[i, 4])
+            # (s (B + rho I)) (B + rho I)^-1 / s = I: the ridge scales with the block
+            prod = scale * (B[i] + 1e-6 * m * np.eye(4)) @ binv[i]
+            np.testing.assert_allclose(prod, np.eye(4), atol=1e-9)
+    one_sided = np.array([[1e-40, 0.0, 0.0, 0.0, 2.0]])
+    jac = oracle_mod.jacobi_inverse(one_sided)
+    np.testing.assert_allclose(jac, [1e40, 1e40, 1e40, 0.5], rtol=1e-14)
 
 
 # ----------------------------------------------------------------------------- Alg. 2
@@ -762,7 +803,7 @@ def test_jittered_ray_origin_stays_in_its_pixel(oracle_mod):
         cam, pix = divmod(ray, per)
         py, px = divmod(pix, cams.width)
         o, d = sc.ray(ray)
-        dc = np.asarray(cams.rot[cam]).reshape(3, 3).T @ d  # camera frame (right, down, forward)
+        dc = np.linalg.solve(np.asarray(cams.rot[cam]).reshape(3, 3), d)  # camera frame (right, down, forward)
         u = dc[0] / dc[2] * cams.fx[cam] + cams.cx[cam]
         v = dc[1] / dc[2] * cams.fy[cam] + cams.cy[cam]
         assert px <= u < px + 1 and py <= v < py + 1, (ray, u, v)
