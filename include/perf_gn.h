@@ -243,15 +243,6 @@ int32_t perf_upsample(const perf_scene_desc* from, const float* d_from, const pe
                       void* stream);
 
 /*
- * Measurement probe (not part of the method): reps passes of one global float atomic add of
- * 1.0 (no return value) to each of d_y[i * stride], i < n (distinct addresses; stride 1 =
- * consecutive, many lanes per L2 request; stride 32 = one 128-byte line per lane, like the
- * J^T scatter's scattered window flushes).  Profiling compares the atomic requests per second
- * of the J^T J v kernel with this probe's.  d_y [n * stride] is caller-owned; asynchronous.
- */
-int32_t perf_atomic_probe(float* d_y, int64_t n, int32_t reps, int32_t stride, void* stream);
-
-/*
  * Preconditioner from given blocks (Sec. III-G), the step perf_build_precond ends with, in the
  * scaled form every PCG kernel applies.  No stored value depends on the scale of the block
  * beyond its inverse square root, so the form stays in FP32 range for any block, including

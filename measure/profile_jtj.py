@@ -1,8 +1,8 @@
 """Profiling script for the J^T J v kernel and its HBM-traffic summary.
 
-  run:        python -m paper_2112_05598_amd.profile_jtj run --workload cfg2 --launches 3 --copy-mib 2048 \
+  run:        python -m measure.profile_jtj run --workload cfg2 --launches 3 --copy-mib 2048 \
                   [--timing-json T.json]
-  summarise:  python -m paper_2112_05598_amd.profile_jtj summarise --fetch F.db --write W.db --out traffic.json \
+  summarise:  python -m measure.profile_jtj summarise --fetch F.db --write W.db --out traffic.json \
                   [--atomic A.db --timing-json T.json]
 
 `run` launches the library's J^T J v product `--launches` times on the named workload (at the
@@ -10,7 +10,7 @@ initial parameters, with a seeded random v), then one plain device-to-device cop
 `--copy-mib` MiB (an elementwise b = a * 1) as the calibration kernel.  Run it under `rocprofv3 --pmc FETCH_SIZE` and,
 separately, under `rocprofv3 --pmc WRITE_SIZE`.
 
-`run` ends with the library's atomic probe (one global float atomic add to each of 32 M
+`run` ends with the atomic probe (measure/atomic_probe.hip) (one global float atomic add to each of 32 M
 distinct addresses, 4 passes) and, with --timing-json, records the J^T J v kernel's and the
 probe's durations (HIP events on the launch stream) for an unprofiled run.
 
@@ -29,7 +29,7 @@ import os
 import sqlite3
 import sys
 
-ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))  # the repository root
 KERNEL_SRC = os.path.join(ROOT, "paper_2112_05598_amd", "csrc", "raymarch.hip")
 JTJ_TAG = "k_ray<3, 0>"  # the J^T J v instantiation of k_ray, FP32 parameters
 COPY_TAGS = ("Mul",)  # the calibration copy: b = a * 1 (reads and writes copy-mib MiB)
@@ -67,19 +67,17 @@ def run(args):
     torch.mul(a, 1.0, out=b)
     torch.cuda.synchronize()
     print(f"[profile] calibration copy of {args.copy_mib} MiB done", flush=True)
-    import ctypes
-    from paper_2112_05598_amd import abi
-    lib = abi.load()
-    st = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+    from measure import probe
+    st = torch.cuda.current_stream(dev).cuda_stream
     timing = {"jtj_ms": jtj_ms}
     # consecutive addresses (stride 1), then one 128-byte line per lane (stride 32); the
     # scattered probe dispatches reps = 2 so the two are told apart in the counter database
     for stride, n_probe, reps in ((1, 32 << 20, 4), (32, 8 << 20, 2)):
         y = torch.zeros(n_probe * stride, dtype=torch.float32, device=dev)
-        abi.check(lib.perf_atomic_probe(ctypes.c_void_p(y.data_ptr()), n_probe, 1, stride, st))  # warm
+        probe.atomic_add(y.data_ptr(), n_probe, 1, stride, st)  # warm
         torch.cuda.synchronize()
         ev[2].record()
-        abi.check(lib.perf_atomic_probe(ctypes.c_void_p(y.data_ptr()), n_probe, reps, stride, st))
+        probe.atomic_add(y.data_ptr(), n_probe, reps, stride, st)
         ev[3].record()
         torch.cuda.synchronize()
         ms = ev[2].elapsed_time(ev[3])

@@ -95,7 +95,6 @@ SIGNATURES = [
     ("perf_footprint", _I32, [_P, _P, _P]),
     ("perf_upsample", _I32, [_P, _P, _P, _P, _P]),
     ("perf_set_jitter", _I32, [_P, ctypes.c_uint32]),
-    ("perf_atomic_probe", _I32, [_P, _I64, _I32, _I32, _P]),
     ("perf_invert_blocks", _I32, [_P, _I64, _I32, _P, _P]),
     ("perf_pack_bf16", _I32, [_P, _P, _I64, _P]),
     ("perf_precond_features", _I32, [_P, _P, _P, _P]),

@@ -391,14 +391,6 @@ int32_t perf_upsample(const perf_scene_desc* from, const float* d_from, const pe
     return PERF_OK;
 }
 
-int32_t perf_atomic_probe(float* d_y, int64_t n, int32_t reps, int32_t stride, void* stream) {
-    if (!d_y && n > 0) return fail(PERF_EINVAL, "null argument");
-    if (n < 0 || reps < 0 || stride < 1) return fail(PERF_EINVAL, "need n, reps >= 0 and stride >= 1");
-    if (n > 0 && (n - 1) > (int64_t)1 << 40) return fail(PERF_EUNSUPPORTED, "probe too large");
-    CK(launch_atomic_probe(d_y, n, reps, stride, (hipStream_t)stream));
-    return PERF_OK;
-}
-
 int32_t perf_invert_blocks(const float* d_blocks, int64_t units, int32_t kind, float* d_out, void* stream) {
     if (units < 0) return fail(PERF_EINVAL, "negative unit count");
     if ((!d_blocks || !d_out) && units > 0) return fail(PERF_EINVAL, "null argument");

@@ -113,7 +113,6 @@ hipError_t launch_pcg_direction(const float* z, float* p, int64_t units, const d
 hipError_t launch_trial(const float* x, const float* delta, float gamma, int64_t units, int nvox, float* xt,
                         uint16_t* xb16, hipStream_t st);
 hipError_t launch_pack_bf16(const float* in, uint16_t* out, int64_t n, hipStream_t st);
-hipError_t launch_atomic_probe(float* y, int64_t n, int reps, int stride, hipStream_t st);
 hipError_t launch_check_finite(const float* p, int64_t n, int* flag, hipStream_t st);
 hipError_t launch_features_finalize(const void* x, int x_dtype, const float* sums, const float* blocks,
                                     int64_t units, float* feat, hipStream_t st);

@@ -375,18 +375,6 @@ unsigned grid_for(int64_t n) {
     return (unsigned)g;
 }
 
-// Measurement probe: reps passes of one global float atomic add (no return) to each of n
-// distinct addresses `stride` floats apart (1: consecutive, many lanes per L2 request; 32:
-// one 128-byte line per lane, one lane per request, like the scattered flushes of the J^T
-// scatter's window slabs); used to calibrate the atomic throughput the scatter is compared
-// against.
-__global__ __launch_bounds__(kVecBlock) void k_atomic_probe(float* __restrict__ y, int64_t n, int reps,
-                                                           int stride) {
-    for (int r = 0; r < reps; ++r)
-        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-            unsafeAtomicAdd(y + i * stride, 1.0f);
-}
-
 }  // namespace
 
 hipError_t launch_zero(float* p, int64_t n, hipStream_t st, const int* done) {
@@ -493,12 +481,6 @@ hipError_t launch_trial(const float* x, const float* delta, float gamma, int64_t
     hipLaunchKernelGGL(k_trial, dim3(grid_for(units)), dim3(kVecBlock), 0, st, reinterpret_cast<const float4*>(x),
                        reinterpret_cast<const float4*>(delta), gamma, units, nvox, reinterpret_cast<float4*>(xt),
                        reinterpret_cast<ushort4*>(xb16));
-    return hipGetLastError();
-}
-
-hipError_t launch_atomic_probe(float* y, int64_t n, int reps, int stride, hipStream_t st) {
-    if (n <= 0 || reps <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_atomic_probe, dim3(grid_for(n)), dim3(kVecBlock), 0, st, y, n, reps, stride);
     return hipGetLastError();
 }
 
