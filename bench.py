@@ -184,7 +184,7 @@ def main():
         # GN time-to-residual: the learned preconditioner, from the same start, until it reaches
         # the objective the timed Jacobi steps ended at (same PCG iterations per step)
         from paper_2112_05598_amd import learned as lrn
-        sc.mlp_set_weights(lrn.load_weights(device="cuda:0"))
+        lrn.load_model(device="cuda:0").install(sc)
         F_target = stats[-1]["F_after"]
         run = lrn.gn_run(sc, x0, "learned", args.steps + 3, args.pcg, F_stop=F_target)
         print(f"[bench] learned: {run['gn_steps']} GN steps, {run['pcg_iters']} PCG iterations, "
@@ -196,7 +196,7 @@ def main():
             "jacobi": {"gn_steps": args.steps, "pcg_iters": sum(s["pcg_iters"] for s in stats), "ms": dt * 1e3},
             "learned": {"gn_steps": run["gn_steps"], "pcg_iters": run["pcg_iters"], "ms": run["ms"],
                         "F": run["F"], "reached": run["F"][-1] <= F_target},
-            "weights": "paper_2112_05598_amd/weights/precond_mlp_bf16.npy"}
+            "model": "paper_2112_05598_amd/weights/precond_mlp.npz"}
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a ray sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w)

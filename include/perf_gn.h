@@ -275,29 +275,48 @@ int32_t perf_pack_bf16(const float* d_in, uint16_t* d_out, int64_t n, void* stre
  *   perf_build_precond) from one traversal at x.  Features per unit: sigma/alpha, colour (3),
  *   log(d + tiny), log(f + tiny), log(1 + sum of sample weights), weighted mean transmittance,
  *   weighted mean colour behind the sample (3), weighted mean sample opacity.
+ * The network's input is the standardised feature vector clamp((f - mu) s, -8, 8), with
+ *   norm [PERF_MLP_NNORM] = (mu[16], s[16]) FP32 (entries 12..15 of each zero: padding).
  * perf_mlp_set_weights: d_w device bfloat16 weights in the packed order W1[64][16] b1[64]
  *   W2[64][64] b2[64] W3[16][64] b3[16] (inputs padded 12 -> 16, outputs 10 -> 16 with zeros);
- *   n_w must equal PERF_MLP_NW.  Copied into the workspace (requires desc.learned = 1).
+ *   n_w must equal PERF_MLP_NW; d_norm the network's standardisation (device FP32); q_fallback:
+ *   a unit whose prediction misses its own normalised block B~ by q = ||L L^T B~ - I||_F^2 >
+ *   q_fallback takes the exact block inverse instead (plain block-Jacobi as the fallback;
+ *   INFINITY never falls back, 0 always).  Copied into the workspace (requires desc.learned = 1).
  * perf_mlp_infer: d_minv [units][12] = (t_d, t_f, L00, L10, L11, L20, L21, L22, L30, L31, L32,
  *   L33) from features and blocks: the network's output is a lower-triangular L (softplus on
  *   the diagonal); M^-1 = D^-1/2 L L^T D^-1/2 with D^-1/2 = diag(t_d, t_d, t_d, t_f) as in
- *   perf_invert_blocks (after the ridge), applied as D^-1/2 L (L^T (D^-1/2 r)); units with
- *   max(d, f) = 0 get 0.
+ *   perf_invert_blocks (after the ridge), applied as D^-1/2 L (L^T (D^-1/2 r)); a unit on the
+ *   fallback holds (-t_d, t_f, e~, 1/s, 0, ...) instead, the block form of perf_invert_blocks with
+ *   t_d negated; units with max(d, f) = 0 get 0.
  * perf_mlp_train_step: one Adam step on a batch of n (feature, block) rows: per-unit error
  *   E = L L^T (Bn + damp I) - I with Bn = D^-1/2 B D^-1/2, so that the target is the damped
  *   normalised inverse (damp = 0: exact block-Jacobi; damp -> inf: Jacobi); the loss is the
  *   mean over the n rows of q = ||E||_F^2 where q <= 4 and 4 sqrt(q) - 4 above (robust against
- *   near-singular blocks); FP32 master weights d_w32 [PERF_MLP_NW],
- *   Adam moments d_m, d_v [PERF_MLP_NW], step count t (>= 1), learning rate lr; writes the
- *   updated bf16 copy to d_wbf16 and the batch loss to d_loss (device float[1]).
+ *   near-singular blocks); FP32 master weights d_w32 [PERF_MLP_NW], d_norm the fixed
+ *   standardisation, Adam moments d_m, d_v [PERF_MLP_NW], step count t (>= 1), learning rate
+ *   lr; writes the updated bf16 copy to d_wbf16 and the batch loss to d_loss (device
+ *   float[1]).  d_grad_scratch [PERF_MLP_NW] FP32 accumulates the gradient; it must be zero on
+ *   entry and is left zero.
+ * perf_mlp_feature_stats: d_norm from n rows of features d_feat [n][12]: per-feature mean and
+ *   s = 1 / max(std, 1e-3), std the population standard deviation, in FP64 and deterministic.
+ * perf_mlp_training_rows: training rows from one traversal's features and blocks: every unit
+ *   some ray touches (max(d, f) > 0) is kept with probability keep, decided by a hash of
+ *   (seed, unit), and the kept rows are written to d_feat_out [cap][12] and d_blocks_out
+ *   [cap][5] in unit order (deterministic); *n_kept (host) receives the number of kept rows,
+ *   of which the first min(n_kept, cap) are written.  Synchronises.
  */
 #define PERF_MLP_NW (64 * 16 + 64 + 64 * 64 + 64 + 16 * 64 + 16)
+#define PERF_MLP_NNORM 32
 int32_t perf_precond_features(perf_scene* s, const void* d_x, float* d_feat, float* d_blocks);
-int32_t perf_mlp_set_weights(perf_scene* s, const uint16_t* d_w, int32_t n_w);
+int32_t perf_mlp_set_weights(perf_scene* s, const uint16_t* d_w, int32_t n_w, const float* d_norm, float q_fallback);
 int32_t perf_mlp_infer(perf_scene* s, const float* d_feat, const float* d_blocks, float* d_minv);
 int32_t perf_mlp_train_step(float* d_w32, uint16_t* d_wbf16, float* d_m, float* d_v, int32_t t, float lr,
-                            float damp, const float* d_feat, const float* d_blocks, int32_t n, float* d_loss,
-                            float* d_grad_scratch, void* stream);
+                            float damp, const float* d_norm, const float* d_feat, const float* d_blocks, int32_t n,
+                            float* d_loss, float* d_grad_scratch, void* stream);
+int32_t perf_mlp_feature_stats(const float* d_feat, int64_t n, float* d_norm, void* stream);
+int32_t perf_mlp_training_rows(perf_scene* s, const float* d_feat, const float* d_blocks, uint32_t seed, float keep,
+                               float* d_feat_out, float* d_blocks_out, int64_t cap, int64_t* n_kept);
 
 #ifdef __cplusplus
 }

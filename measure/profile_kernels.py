@@ -1,24 +1,25 @@
-"""Profiling script for the J^T J v kernel and its HBM-traffic summary.
+"""Profiling script for the library's hot kernels and their rocprofv3 summaries.
 
-  run:        python -m measure.profile_jtj run --workload cfg2 --launches 3 --copy-mib 2048 \
+  run:        python -m measure.profile_kernels run --workload cfg2 --launches 2 --copy-mib 2048 \
                   [--timing-json T.json]
-  summarise:  python -m measure.profile_jtj summarise --fetch F.db --write W.db --out traffic.json \
+  summarise:  python -m measure.profile_kernels summarise --fetch F.db --write W.db --out traffic.json \
                   [--atomic A.db --timing-json T.json]
+  counters:   python -m measure.profile_kernels counters --db P1.db [--db P2.db ...] --out counters.json
 
-`run` launches the library's J^T J v product `--launches` times on the named workload (at the
-initial parameters, with a seeded random v), then one plain device-to-device copy of
-`--copy-mib` MiB (an elementwise b = a * 1) as the calibration kernel.  Run it under `rocprofv3 --pmc FETCH_SIZE` and,
-separately, under `rocprofv3 --pmc WRITE_SIZE`.
+`run` launches, on the named workload at the initial parameters: the J^T J v product `--launches`
+times (seeded random v), the gradient + exact-block pass, the feature pass of the learned
+preconditioner, the MLP inference over every unit and four training steps on 16384 rows; then
+one plain device-to-device copy of `--copy-mib` MiB (an elementwise b = a * 1) as the
+calibration kernel of the HBM counters, and the atomic probe (measure/atomic_probe.hip).  With
+--timing-json it records the durations (HIP events on the launch stream) of an unprofiled run.
+Run it under `rocprofv3 --pmc <counters>` once per counter set.
 
-`run` ends with the atomic probe (measure/atomic_probe.hip) (one global float atomic add to each of 32 M
-distinct addresses, 4 passes) and, with --timing-json, records the J^T J v kernel's and the
-probe's durations (HIP events on the launch stream) for an unprofiled run.
-
-`summarise` reads the two rocprofv3 result databases, averages each counter per dispatch of the
-J^T J v kernel, scales it by (known copy bytes / counted copy bytes) of the calibration copy,
-and writes the HBM bytes per dispatch together with the sha256 of the kernel source they
-were measured on.  With --atomic (a TCC_ATOMIC pass) and --timing-json it adds the L2 atomic
-requests per second of the J^T J v kernel against those of the probe.
+`summarise` reads a FETCH_SIZE and a WRITE_SIZE database, averages each counter per dispatch of the
+J^T J v kernel, scales it by (known copy bytes / counted copy bytes) of the calibration copy, and
+writes the HBM bytes per dispatch together with the sha256 of the kernel source they were
+measured on; with --atomic (a TCC_ATOMIC pass) and --timing-json it adds the L2 atomic requests
+per second of the J^T J v kernel against those of the probe.  `counters` averages every counter of
+the given databases per dispatch of each kernel.
 """
 from __future__ import annotations
 
@@ -33,6 +34,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))  # the reposi
 KERNEL_SRC = os.path.join(ROOT, "paper_2112_05598_amd", "csrc", "raymarch.hip")
 JTJ_TAG = "k_ray<3, 0>"  # the J^T J v instantiation of k_ray, FP32 parameters
 COPY_TAGS = ("Mul",)  # the calibration copy: b = a * 1 (reads and writes copy-mib MiB)
+KERNELS = {"k_ray<3, 0>": "jtj", "k_ray<4, 0>": "grad", "k_ray<5, 0>": "feat", "k_mlp_infer": "mlp_infer",
+           "k_mlp_train": "mlp_train"}
 
 
 def kernel_sha() -> str:
@@ -44,32 +47,62 @@ def run(args):
         sys.path.insert(0, ROOT)
     import torch
     import perf_synth as ps
-    from paper_2112_05598_amd.scene import Scene
+    from paper_2112_05598_amd.scene import Scene, mlp_feature_stats, mlp_train_step
+    from paper_2112_05598_amd import learned
     w = ps.workload(args.workload)
     dev = torch.device("cuda:0")
-    sc = Scene(w.spec, w.cams, None, device="cuda:0")
+    sc = Scene(w.spec, w.cams, None, device="cuda:0", learned=True)
+    H, _ = sc.render_residuals(torch.from_numpy(w.x_gt).to(dev))
+    targets = H.clone()
+    sc.set_targets(targets)
     x = torch.from_numpy(w.x_init).to(dev)
     v = torch.from_numpy(ps.random_vector(sc.n_params, 1)).to(dev)
-    for i in range(args.launches):
-        sc.apply_JtJ(x, v)
-        torch.cuda.synchronize()
-        print(f"[profile] J^T J v launch {i + 1}/{args.launches} done", flush=True)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
-    ev[0].record()
-    sc.apply_JtJ(x, v)
-    ev[1].record()
-    torch.cuda.synchronize()
-    jtj_ms = ev[0].elapsed_time(ev[1])
-    n = args.copy_mib * (1 << 20) // 4
-    a = torch.ones(n, dtype=torch.float32, device=dev)
+    timing = {}
+
+    def timed(name, fn):
+        torch.cuda.synchronize()
+        ev[0].record()
+        out = fn()
+        ev[1].record()
+        torch.cuda.synchronize()
+        timing[name] = ev[0].elapsed_time(ev[1])
+        print(f"[profile] {name}: {timing[name]:.3f} ms", flush=True)
+        return out
+
+    for i in range(args.launches):
+        timed("jtj_ms", lambda: sc.apply_JtJ(x, v))
+    timed("grad_ms", lambda: sc.build_precond(x, "none"))
+    feat, blocks = timed("features_ms", lambda: sc.features(x))
+    rows_f, rows_b, _ = sc.training_rows(feat, blocks, 1, 0.05, 200000)
+    norm = mlp_feature_stats(rows_f)
+    model = learned.load_model(device="cuda:0") if os.path.exists(learned.WEIGHTS) else None
+    if model is None:
+        import numpy as np
+        wbf = torch.from_numpy(learned.init_weights(0).astype(np.float32)).to(dev).to(torch.bfloat16)
+        model = learned.Model(wbf, norm)
+    model.install(sc)
+    timed("mlp_infer_ms", lambda: sc.mlp_infer(feat, blocks))
+    timing["units"] = sc.n_units
+    n = min(16384, rows_f.shape[0])
+    w32 = model.w_bf16.float().clone()
+    wbf = model.w_bf16.clone()
+    m, vv, g = torch.zeros_like(w32), torch.zeros_like(w32), torch.zeros_like(w32)
+    loss = torch.zeros(1, device=dev)
+    fb, bb = rows_f[:n].contiguous(), rows_b[:n].contiguous()
+    for t in range(1, 5):
+        timed("mlp_train_ms", lambda: mlp_train_step(w32, wbf, m, vv, t, 1e-4, norm, fb, bb, loss, g))
+    timing["train_rows"] = n
+    n_copy = args.copy_mib * (1 << 20) // 4
+    a = torch.ones(n_copy, dtype=torch.float32, device=dev)
     b = torch.empty_like(a)
     torch.cuda.synchronize()
     torch.mul(a, 1.0, out=b)
     torch.cuda.synchronize()
     print(f"[profile] calibration copy of {args.copy_mib} MiB done", flush=True)
+    del a, b
     from measure import probe
     st = torch.cuda.current_stream(dev).cuda_stream
-    timing = {"jtj_ms": jtj_ms}
     # consecutive addresses (stride 1), then one 128-byte line per lane (stride 32); the
     # scattered probe dispatches reps = 2 so the two are told apart in the counter database
     for stride, n_probe, reps in ((1, 32 << 20, 4), (32, 8 << 20, 2)):
@@ -83,7 +116,7 @@ def run(args):
         ms = ev[2].elapsed_time(ev[3])
         assert float(y[0]) == reps + 1 and float(y[(n_probe - 1) * stride]) == reps + 1
         print(f"[profile] atomic probe, stride {stride}: {n_probe * reps} atomics in {ms:.3f} ms "
-              f"({n_probe * reps / ms / 1e6:.2f} G atomics/s); J^T J v {jtj_ms:.2f} ms", flush=True)
+              f"({n_probe * reps / ms / 1e6:.2f} G atomics/s)", flush=True)
         timing[f"probe{stride}_ms"] = ms
         timing[f"probe{stride}_atomics"] = n_probe * reps
         del y
@@ -168,12 +201,31 @@ def summarise(args):
     print(json.dumps(out, indent=1))
 
 
+def counters(args):
+    """Every counter of the given databases, averaged per dispatch of each profiled kernel."""
+    out = {"kernel_sha": kernel_sha(), "workload": args.workload, "kernels": {}}
+    for db in args.db:
+        con = sqlite3.connect(db)
+        tab = next(r[0] for r in con.execute("select name from sqlite_master where type in ('table', 'view')")
+                   if r[0].startswith("counters_collection"))
+        names = [r[0] for r in con.execute(f"select distinct counter_name from '{tab}'")]
+        for c in names:
+            for kname, (val, disp) in _per_dispatch(db, c).items():
+                short = next((v for k, v in KERNELS.items() if k in kname), None)
+                if short is None:
+                    continue
+                out["kernels"].setdefault(short, {"kernel": kname})[c] = {"per_dispatch": val, "dispatches": disp}
+    with open(args.out, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out, indent=1))
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
     r = sub.add_parser("run")
     r.add_argument("--workload", default="cfg2")
-    r.add_argument("--launches", type=int, default=3)
+    r.add_argument("--launches", type=int, default=2)
     r.add_argument("--copy-mib", type=int, default=2048)
     r.add_argument("--timing-json", default="")
     s = sub.add_parser("summarise")
@@ -184,8 +236,12 @@ def main():
     s.add_argument("--out", required=True)
     s.add_argument("--atomic", default="")
     s.add_argument("--timing-json", default="")
+    c = sub.add_parser("counters")
+    c.add_argument("--db", action="append", required=True)
+    c.add_argument("--workload", default="cfg2")
+    c.add_argument("--out", required=True)
     args = ap.parse_args()
-    run(args) if args.cmd == "run" else summarise(args)
+    {"run": run, "summarise": summarise, "counters": counters}[args.cmd](args)
 
 
 if __name__ == "__main__":

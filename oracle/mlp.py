@@ -6,10 +6,16 @@ per-unit features.  Conventions, identical to the product's:
 
   weights, packed: W1[64][16] b1[64] W2[64][64] b2[64] W3[16][64] b3[16]
                    (inputs padded 12 -> 16, outputs 10 -> 16 with zeros)
+  standardisation: norm = (mu[16], s[16]) from the training features: mu the mean and
+                   s = 1 / max(std, 1e-3) per feature (0 for the padding); the network's input
+                   is x = clamp((feature - mu) s, -CLAMP, CLAMP)
   network:         h1 = relu(W1 x + b1), h2 = relu(W2 h1 + b2), o = W3 h2 + b3
   factor:          L lower triangular from o[0:10] row by row, softplus on the diagonal
   ridge:           rho = 1e-6 max(d, f); D = diag(d, d, d, f) + rho I
   normalised block B~ = D^-1/2 (B + rho I) D^-1/2,  M^-1 = D^-1/2 L L^T D^-1/2
+  fallback:        a unit whose prediction misses its own normalised block by
+                   q = ||L L^T B~ - I||_F^2 > q_fallback takes the exact block inverse
+                   (B + rho I)^-1 instead (plain block-Jacobi)
   loss per unit:   q = || L L^T (B~ + damp I) - I ||_F^2 (damp = 0: the exact inverse is the
                    target; larger damp moves it towards plain Jacobi), made robust above KAPPA:
                    q if q <= KAPPA, else 2 sqrt(KAPPA q) - KAPPA (linear in the norm), averaged
@@ -27,6 +33,8 @@ TRIL = [(0, 0), (1, 0), (1, 1), (2, 0), (2, 1), (2, 2), (3, 0), (3, 1), (3, 2), 
 DIAG = [0, 2, 5, 9]
 RIDGE = 1e-6
 KAPPA = 4.0
+CLAMP = 8.0
+STD_FLOOR = 1e-3
 
 
 def bf16_round(w: np.ndarray) -> np.ndarray:
@@ -96,7 +104,28 @@ def features(x: np.ndarray, sums: np.ndarray, blocks: np.ndarray) -> np.ndarray:
     return f
 
 
-def forward(w: np.ndarray, feat: np.ndarray, emulate_bf16: bool = False):
+def feature_stats(feat: np.ndarray) -> np.ndarray:
+    """norm [32] = (mu[16], s[16]) of a training set: per-feature mean and 1 / max(std, 1e-3),
+    std the population standard deviation; zeros for the 4 padding inputs."""
+    f = np.asarray(feat, dtype=np.float64).reshape(-1, N_IN)
+    mu = f.mean(axis=0)
+    sd = np.sqrt(np.maximum((f * f).mean(axis=0) - mu * mu, 0.0))
+    norm = np.zeros(2 * N_IN_PAD)
+    norm[:N_IN] = mu
+    norm[N_IN_PAD:N_IN_PAD + N_IN] = 1.0 / np.maximum(sd, STD_FLOOR)
+    return norm
+
+
+def standardise(norm: np.ndarray, feat: np.ndarray) -> np.ndarray:
+    """[n, 16] network inputs: clamp((feature - mu) s, -CLAMP, CLAMP), zero padding."""
+    norm = np.asarray(norm, dtype=np.float64).reshape(-1)
+    f = np.asarray(feat, dtype=np.float64).reshape(-1, N_IN)
+    x = np.zeros((f.shape[0], N_IN_PAD))
+    x[:, :N_IN] = np.clip((f - norm[:N_IN]) * norm[N_IN_PAD:N_IN_PAD + N_IN], -CLAMP, CLAMP)
+    return x
+
+
+def forward(w: np.ndarray, norm: np.ndarray, feat: np.ndarray, emulate_bf16: bool = False):
     """Raw outputs [n, 10] and the activations needed for the backward pass.
 
     emulate_bf16 rounds the input and both hidden activations to bfloat16 before the
@@ -104,9 +133,7 @@ def forward(w: np.ndarray, feat: np.ndarray, emulate_bf16: bool = False):
     stay exact here)."""
     p = unpack(w)
     rnd = bf16_round if emulate_bf16 else (lambda a: a)
-    x = np.zeros((feat.shape[0], N_IN_PAD))
-    x[:, :N_IN] = feat
-    x = rnd(x)
+    x = rnd(standardise(norm, feat))
     z1 = x @ p["W1"].T + p["b1"]
     h1 = rnd(np.maximum(z1, 0.0))
     z2 = h1 @ p["W2"].T + p["b2"]
@@ -147,22 +174,36 @@ def normalised_block(blocks: np.ndarray):
     return Bn, dis, live
 
 
-def minv(w: np.ndarray, feat: np.ndarray, blocks: np.ndarray, emulate_bf16: bool = False) -> np.ndarray:
-    """[n, 4, 4] M^-1 = D^-1/2 L L^T D^-1/2 (zero for units with no rays)."""
-    raw, _ = forward(w, feat, emulate_bf16)
+def prediction_error(L: np.ndarray, Bn: np.ndarray) -> np.ndarray:
+    """q = ||L L^T B~ - I||_F^2 per unit."""
+    E = (L @ np.transpose(L, (0, 2, 1))) @ Bn - np.eye(4)[None]
+    return (E * E).sum(axis=(1, 2))
+
+
+def minv(w: np.ndarray, norm: np.ndarray, feat: np.ndarray, blocks: np.ndarray, emulate_bf16: bool = False,
+         q_fallback: float = np.inf, return_fallback: bool = False):
+    """[n, 4, 4] M^-1 = D^-1/2 L L^T D^-1/2, zero for units with no rays; units whose q exceeds
+    q_fallback get the exact block inverse (B + rho I)^-1.  With return_fallback, also the
+    [n] mask of those units and their q."""
+    raw, _ = forward(w, norm, feat, emulate_bf16)
     L = factor(raw)
-    _, dis, live = normalised_block(blocks)
-    P = L @ np.transpose(L, (0, 2, 1))
-    M = dis[:, :, None] * P * dis[:, None, :]
+    Bn, dis, live = normalised_block(blocks)
+    q = prediction_error(L, Bn)
+    fb = live & (q > q_fallback)
+    N = L @ np.transpose(L, (0, 2, 1))
+    if np.any(fb):
+        N[fb] = np.linalg.inv(Bn[fb])
+    M = dis[:, :, None] * N * dis[:, None, :]
     M[~live] = 0.0
-    return M
+    return (M, fb, q) if return_fallback else M
 
 
-def loss_and_grad(w: np.ndarray, feat: np.ndarray, blocks: np.ndarray, damp: float = 0.0):
+def loss_and_grad(w: np.ndarray, norm: np.ndarray, feat: np.ndarray, blocks: np.ndarray, damp: float = 0.0):
     """Mean over the n given units of the robust ||L L^T (B~ + damp I) - I||_F^2 (zero for
-    units no ray touches) and its gradient w.r.t. the packed weights."""
+    units no ray touches) and its gradient w.r.t. the packed weights (the standardisation is
+    fixed, not trained)."""
     p = unpack(w)
-    raw, (x, z1, h1, z2, h2) = forward(w, feat)
+    raw, (x, z1, h1, z2, h2) = forward(w, norm, feat)
     L = factor(raw)
     Bn, _, live = normalised_block(blocks)
     Bn = Bn + damp * np.where(live, 1.0, 0.0)[:, None, None] * np.eye(4)[None]

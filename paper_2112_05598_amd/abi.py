@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(PKG, "libperf_gn.so")
 PERF_MAX_LAYERS = 8
 PERF_MAX_PCG = 256
 PERF_MLP_NW = 64 * 16 + 64 + 64 * 64 + 64 + 16 * 64 + 16
+PERF_MLP_NNORM = 32
 
 PERF_OK, PERF_EINVAL, PERF_ENOMEM, PERF_EDEVICE, PERF_ENUMERIC, PERF_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 PERF_F32, PERF_BF16 = 0, 1
@@ -98,9 +99,13 @@ SIGNATURES = [
     ("perf_invert_blocks", _I32, [_P, _I64, _I32, _P, _P]),
     ("perf_pack_bf16", _I32, [_P, _P, _I64, _P]),
     ("perf_precond_features", _I32, [_P, _P, _P, _P]),
-    ("perf_mlp_set_weights", _I32, [_P, _P, _I32]),
+    ("perf_mlp_set_weights", _I32, [_P, _P, _I32, _P, ctypes.c_float]),
     ("perf_mlp_infer", _I32, [_P, _P, _P, _P]),
-    ("perf_mlp_train_step", _I32, [_P, _P, _P, _P, _I32, ctypes.c_float, ctypes.c_float, _P, _P, _I32, _P, _P, _P]),
+    ("perf_mlp_train_step", _I32, [_P, _P, _P, _P, _I32, ctypes.c_float, ctypes.c_float, _P, _P, _P, _I32, _P, _P,
+                                   _P]),
+    ("perf_mlp_feature_stats", _I32, [_P, _I64, _P, _P]),
+    ("perf_mlp_training_rows", _I32, [_P, _P, _P, ctypes.c_uint32, ctypes.c_float, _P, _P, _I64,
+                                      ctypes.POINTER(_I64)]),
 ]
 
 _lib = None

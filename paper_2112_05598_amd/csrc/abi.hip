@@ -27,6 +27,8 @@ struct perf_scene {
     int* iflags;
     float *vr, *vz, *vp, *vAp, *vdelta, *vxt, *blocks, *minv, *feat, *featsum;
     uint16_t *xb16, *mlpw;
+    float* mlpnorm;
+    float q_fallback;
     bool mlp_ready;
     double host_scalars[S_COUNT];
     double host_hist[4 * PERF_MAX_PCG];
@@ -155,6 +157,7 @@ Layout make_layout(const perf_scene_desc& d, int n_cams) {
         L.feat = take(sizeof(float) * 12 * (size_t)units);
         L.footprint = take(sizeof(float) * 6 * (size_t)units);  // per-unit feature sums
         L.mlpw = take(sizeof(uint16_t) * PERF_MLP_NW);
+        L.mlpnorm = take(sizeof(float) * PERF_MLP_NNORM);
     }
     L.total = o;
     return L;
@@ -227,6 +230,8 @@ int32_t perf_init_scene(const perf_scene_desc* desc, const perf_camera* cams, in
     s->feat = desc->learned ? (float*)(s->ws + L.feat) : nullptr;
     s->featsum = desc->learned ? (float*)(s->ws + L.footprint) : nullptr;
     s->mlpw = desc->learned ? (uint16_t*)(s->ws + L.mlpw) : nullptr;
+    s->mlpnorm = desc->learned ? (float*)(s->ws + L.mlpnorm) : nullptr;
+    s->q_fallback = INFINITY;
     s->mlp_ready = false;
     hipError_t e = hipMemcpyAsync(s->cams, hc, sizeof(DevCam) * n_cams, hipMemcpyHostToDevice, s->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
@@ -453,11 +458,14 @@ int32_t perf_precond_features(perf_scene* s, const void* d_x, float* d_feat, flo
     return features_pass(s, d_x, d_x, s->desc.param_dtype, d_feat, blocks);
 }
 
-int32_t perf_mlp_set_weights(perf_scene* s, const uint16_t* d_w, int32_t n_w) {
-    if (!s || !d_w) return fail(PERF_EINVAL, "null argument");
+int32_t perf_mlp_set_weights(perf_scene* s, const uint16_t* d_w, int32_t n_w, const float* d_norm, float q_fallback) {
+    if (!s || !d_w || !d_norm) return fail(PERF_EINVAL, "null argument");
     if (!s->mlpw) return fail(PERF_EUNSUPPORTED, "the scene was created without learned = 1");
     if (n_w != PERF_MLP_NW) return fail(PERF_EINVAL, "expected %d weights, got %d", PERF_MLP_NW, n_w);
+    if (isnan(q_fallback) || q_fallback < 0.0f) return fail(PERF_EINVAL, "q_fallback must be >= 0 (INFINITY: never)");
     CK(hipMemcpyAsync(s->mlpw, d_w, sizeof(uint16_t) * PERF_MLP_NW, hipMemcpyDeviceToDevice, s->stream));
+    CK(hipMemcpyAsync(s->mlpnorm, d_norm, sizeof(float) * PERF_MLP_NNORM, hipMemcpyDeviceToDevice, s->stream));
+    s->q_fallback = q_fallback;
     s->mlp_ready = true;
     return PERF_OK;
 }
@@ -465,19 +473,41 @@ int32_t perf_mlp_set_weights(perf_scene* s, const uint16_t* d_w, int32_t n_w) {
 int32_t perf_mlp_infer(perf_scene* s, const float* d_feat, const float* d_blocks, float* d_minv) {
     if (!s || !d_feat || !d_blocks || !d_minv) return fail(PERF_EINVAL, "null argument");
     if (!s->mlp_ready) return fail(PERF_EINVAL, "no weights (perf_mlp_set_weights)");
-    CK(launch_mlp_infer(s->mlpw, d_feat, d_blocks, s->units, d_minv, s->stream));
+    CK(launch_mlp_infer(s->mlpw, s->mlpnorm, s->q_fallback, d_feat, d_blocks, s->units, d_minv, s->stream));
     return PERF_OK;
 }
 
 int32_t perf_mlp_train_step(float* d_w32, uint16_t* d_wbf16, float* d_m, float* d_v, int32_t t, float lr,
-                            float damp, const float* d_feat, const float* d_blocks, int32_t n, float* d_loss, float* d_grad_scratch,
-                            void* stream) {
-    if (!d_w32 || !d_wbf16 || !d_m || !d_v || !d_loss || !d_grad_scratch) return fail(PERF_EINVAL, "null argument");
+                            float damp, const float* d_norm, const float* d_feat, const float* d_blocks, int32_t n,
+                            float* d_loss, float* d_grad_scratch, void* stream) {
+    if (!d_w32 || !d_wbf16 || !d_m || !d_v || !d_loss || !d_grad_scratch || !d_norm)
+        return fail(PERF_EINVAL, "null argument");
     if (n < 0 || (n > 0 && (!d_feat || !d_blocks))) return fail(PERF_EINVAL, "bad batch");
     if (t < 1 || !(lr > 0.0f)) return fail(PERF_EINVAL, "need t >= 1 and lr > 0");
     if (!(damp >= 0.0f && damp <= 1e6f)) return fail(PERF_EINVAL, "damp must be in [0, 1e6]");
-    CK(launch_mlp_train(d_w32, d_wbf16, d_m, d_v, t, lr, damp, d_feat, d_blocks, n, d_loss, d_grad_scratch,
+    CK(launch_mlp_train(d_w32, d_wbf16, d_m, d_v, t, lr, damp, d_norm, d_feat, d_blocks, n, d_loss, d_grad_scratch,
                         (hipStream_t)stream));
+    return PERF_OK;
+}
+
+int32_t perf_mlp_feature_stats(const float* d_feat, int64_t n, float* d_norm, void* stream) {
+    if (!d_norm || (n > 0 && !d_feat)) return fail(PERF_EINVAL, "null argument");
+    if (n < 0) return fail(PERF_EINVAL, "negative row count");
+    CK(launch_feature_stats(d_feat, n, d_norm, (hipStream_t)stream));
+    return PERF_OK;
+}
+
+int32_t perf_mlp_training_rows(perf_scene* s, const float* d_feat, const float* d_blocks, uint32_t seed, float keep,
+                               float* d_feat_out, float* d_blocks_out, int64_t cap, int64_t* n_kept) {
+    if (!s || !d_feat || !d_blocks || !n_kept) return fail(PERF_EINVAL, "null argument");
+    if (cap < 0 || (cap > 0 && (!d_feat_out || !d_blocks_out))) return fail(PERF_EINVAL, "bad output capacity");
+    if (!(keep >= 0.0f && keep <= 1.0f)) return fail(PERF_EINVAL, "keep must be in [0, 1]");
+    long long* counts = reinterpret_cast<long long*>(s->partials);  // kVecGrid + 1 entries
+    CK(launch_training_rows(d_feat, d_blocks, s->units, seed, keep, d_feat_out, d_blocks_out, cap, counts, s->stream));
+    long long total = 0;
+    CK(hipMemcpyAsync(&total, counts + kVecGrid, sizeof(long long), hipMemcpyDeviceToHost, s->stream));
+    CK(hipStreamSynchronize(s->stream));
+    *n_kept = total;
     return PERF_OK;
 }
 
@@ -485,7 +515,7 @@ int32_t perf_mlp_train_step(float* d_w32, uint16_t* d_wbf16, float* d_m, float* 
 static int32_t learned_minv(perf_scene* s, const void* xg, const float* x32) {
     int32_t rc = features_pass(s, xg, x32, PERF_F32, s->feat, s->blocks);
     if (rc != PERF_OK) return rc;
-    CK(launch_mlp_infer(s->mlpw, s->feat, s->blocks, s->units, s->minv, s->stream));
+    CK(launch_mlp_infer(s->mlpw, s->mlpnorm, s->q_fallback, s->feat, s->blocks, s->units, s->minv, s->stream));
     return PERF_OK;
 }
 

@@ -7,6 +7,11 @@
 // triangular factor L (softplus on the diagonal), so M^-1 = D^-1/2 L L^T D^-1/2 is symmetric
 // positive definite by construction; D = diag(d, d, d, f) + ridge.
 //
+// The network's input is the standardised feature vector clamp((f - mu) s, -8, 8), with mu and
+// s = 1 / max(std, 1e-3) taken from the training set (norm [32] = mu[16], s[16]).  At inference
+// a unit whose prediction misses its own normalised block by q = ||L L^T B~ - I||_F^2 above a
+// threshold takes the exact block inverse instead (plain block-Jacobi as the fallback).
+//
 // Every product is C[M x N] = A[M x K] * Bt[N x K]^T with both operands bfloat16 in LDS,
 // K contiguous, rows padded to avoid bank conflicts.  One wave owns a tile of 64 units.
 // MFMA operand layout (checked on the device): lane l holds A[l%32][4(l/32)+j] and
@@ -31,6 +36,7 @@ constexpr int TU = 64;   // units per wave tile
 constexpr int LD16 = 20, LD32 = 36, LD64 = 68;  // padded row strides (elements)
 constexpr float kRidge = 1e-6f;
 constexpr float kKappa = 4.0f;  // per-unit loss is quadratic up to ||E||^2 = kKappa, linear in ||E|| above
+constexpr float kClamp = 8.0f;  // standardised inputs are clamped to [-kClamp, kClamp]
 
 __device__ __forceinline__ unsigned short f2bf(float f) {
     const unsigned u = __float_as_uint(f);
@@ -170,12 +176,13 @@ __device__ __forceinline__ void make_L(const float raw[NO], float L[4][4]) {
         for (int j = 0; j <= i; ++j, ++k) L[i][j] = (i == j) ? softplus(raw[k]) : raw[k];
 }
 
-// features of one unit into the X tile row (bf16, zero padded)
-__device__ __forceinline__ void load_features(const float* __restrict__ feat, int64_t unit, int64_t n, lds_bf* Xrow,
-                                              lds_bf* Xt, int col) {
+// standardised features of one unit into the X tile row (bf16, zero padded): clamp((f - mu) s)
+__device__ __forceinline__ void load_features(const float* __restrict__ feat, const float* __restrict__ norm,
+                                              int64_t unit, int64_t n, lds_bf* Xrow, lds_bf* Xt, int col) {
 #pragma unroll
     for (int i = 0; i < NIP; ++i) {
-        const float v = (unit < n && i < NIN) ? feat[NIN * unit + i] : 0.0f;
+        float v = 0.0f;
+        if (unit < n && i < NIN) v = fminf(fmaxf((feat[NIN * unit + i] - norm[i]) * norm[NIP + i], -kClamp), kClamp);
         const unsigned short q = f2bf(v);
         Xrow[i] = q;
         if (Xt) Xt[i * LD64 + col] = q;
@@ -190,6 +197,7 @@ __device__ __forceinline__ void load_features(const float* __restrict__ feat, in
 constexpr int kInferWaves = 4;
 
 __global__ __launch_bounds__(64 * kInferWaves) void k_mlp_infer(const unsigned short* __restrict__ w,
+                                                                const float* __restrict__ norm, float q_fallback,
                                                                 const float* __restrict__ feat,
                                                                 const float* __restrict__ blocks, int64_t units,
                                                                 float* __restrict__ minv) {
@@ -207,7 +215,7 @@ __global__ __launch_bounds__(64 * kInferWaves) void k_mlp_infer(const unsigned s
     const int64_t n_tiles = (units + TU - 1) / TU;
     for (int64_t tile = (int64_t)blockIdx.x * kInferWaves + wv; tile < n_tiles; tile += (int64_t)gridDim.x * kInferWaves) {
         const int64_t unit = tile * TU + l;
-        load_features(feat, unit, units, Xs + l * LD16, nullptr, 0);
+        load_features(feat, norm, unit, units, Xs + l * LD16, nullptr, 0);
         forward_tile(W, Xs, H1s, H2s, Os, nullptr, nullptr);
         if (unit < units) {
             const float* b = blocks + 5 * unit;
@@ -222,12 +230,46 @@ __global__ __launch_bounds__(64 * kInferWaves) void k_mlp_infer(const unsigned s
                 for (int i = 0; i < NO; ++i) raw[i] = Os[l * 17 + i];
                 float L[4][4];
                 make_L(raw, L);
-                // scaled form: D^-1/2 (in double: d may be subnormal) and the factor L, row by row
+                // D^-1/2 and the normalised coupling in double (d may be subnormal)
                 const double rho = (double)kRidge * m;
-                const float td = (float)(1.0 / sqrt((double)d + rho)), tf = (float)(1.0 / sqrt((double)f + rho));
-                o[0] = make_float4(td, tf, L[0][0], L[1][0]);
-                o[1] = make_float4(L[1][1], L[2][0], L[2][1], L[2][2]);
-                o[2] = make_float4(L[3][0], L[3][1], L[3][2], L[3][3]);
+                const double tdd = 1.0 / sqrt((double)d + rho), tfd = 1.0 / sqrt((double)f + rho);
+                const double a0 = b[1] * tdd * tfd, a1 = b[2] * tdd * tfd, a2 = b[3] * tdd * tfd;
+                const float td = (float)tdd, tf = (float)tfd;
+                const float e[3] = {(float)a0, (float)a1, (float)a2};
+                // q = ||L L^T B~ - I||_F^2 with B~ = [[I, e], [e^T, 1]]
+                float P[4][4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        float p = 0.0f;
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) p += L[i][k] * L[j][k];
+                        P[i][j] = p;
+                    }
+                float q = 0.0f;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) {
+                        const float v = P[i][j] + P[i][3] * e[j] - (i == j ? 1.0f : 0.0f);
+                        q += v * v;
+                    }
+                    const float v3 = P[i][0] * e[0] + P[i][1] * e[1] + P[i][2] * e[2] + P[i][3] - (i == 3 ? 1.0f : 0.0f);
+                    q += v3 * v3;
+                }
+                if (q > q_fallback) {
+                    // the exact block inverse in the elimination form of the block preconditioner,
+                    // marked by a negative t_d
+                    const double is = 1.0 / (1.0 - (a0 * a0 + a1 * a1 + a2 * a2));
+                    o[0] = make_float4(-td, tf, e[0], e[1]);
+                    o[1] = make_float4(e[2], (float)is, 0.0f, 0.0f);
+                    o[2] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                } else {
+                    o[0] = make_float4(td, tf, L[0][0], L[1][0]);
+                    o[1] = make_float4(L[1][1], L[2][0], L[2][1], L[2][2]);
+                    o[2] = make_float4(L[3][0], L[3][1], L[3][2], L[3][3]);
+                }
             }
         }
     }
@@ -236,6 +278,7 @@ __global__ __launch_bounds__(64 * kInferWaves) void k_mlp_infer(const unsigned s
 // ------------------------------------------------------------------ training step
 // One wave per workgroup (the activations of a tile are kept in both orientations).
 __global__ __launch_bounds__(64) void k_mlp_train(const unsigned short* __restrict__ w,
+                                                  const float* __restrict__ norm,
                                                   const float* __restrict__ feat, const float* __restrict__ blocks,
                                                   int n, float inv_n, float damp, float* __restrict__ grad,
                                                   float* __restrict__ loss) {
@@ -248,7 +291,7 @@ __global__ __launch_bounds__(64) void k_mlp_train(const unsigned short* __restri
     load_weights(w, W, (lds_bf*)sW2t, (lds_bf*)sW3t);
     const int l = lane();
     const int64_t unit = (int64_t)blockIdx.x * TU + l;
-    load_features(feat, unit, n, (lds_bf*)sX + l * LD16, (lds_bf*)sXt, l);
+    load_features(feat, norm, unit, n, (lds_bf*)sX + l * LD16, (lds_bf*)sXt, l);
     forward_tile(W, (lds_bf*)sX, (lds_bf*)sH1, (lds_bf*)sH2, sO, (lds_bf*)sH1t, (lds_bf*)sH2t);
 
     // robust loss of E = L L^T (B~ + damp I) - I for this unit and its gradient w.r.t. the raw outputs
@@ -443,30 +486,73 @@ __global__ void k_adam(float* __restrict__ w32, unsigned short* __restrict__ wbf
     }
 }
 
+// Standardisation of a training set: workgroup i sums feature i over the n rows in FP64, in a
+// fixed order (deterministic), and writes mu_i and s_i = 1 / max(std_i, 1e-3), std the
+// population standard deviation; the padding inputs get 0.
+constexpr int kStatsBlock = 256;
+__global__ __launch_bounds__(kStatsBlock) void k_feature_stats(const float* __restrict__ feat, int64_t n,
+                                                               float* __restrict__ norm) {
+    __shared__ double red[2][kStatsBlock];
+    const int i = blockIdx.x;
+    double s1 = 0.0, s2 = 0.0;
+    for (int64_t r = threadIdx.x; r < n; r += kStatsBlock) {
+        const double v = feat[NIN * r + i];
+        s1 += v;
+        s2 += v * v;
+    }
+    red[0][threadIdx.x] = s1;
+    red[1][threadIdx.x] = s2;
+    __syncthreads();
+    for (int h = kStatsBlock / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + h];
+            red[1][threadIdx.x] += red[1][threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double mu = n > 0 ? red[0][0] / (double)n : 0.0;
+        const double var = n > 0 ? fmax(red[1][0] / (double)n - mu * mu, 0.0) : 0.0;
+        norm[i] = (float)mu;
+        norm[NIP + i] = (float)(1.0 / fmax(sqrt(var), 1e-3));
+        if (i < NIP - NIN) {
+            norm[NIN + i] = 0.0f;
+            norm[NIP + NIN + i] = 0.0f;
+        }
+    }
+}
+
 __global__ void k_zero1(float* p, int n) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0.0f;
 }
 
 }  // namespace
 
-hipError_t launch_mlp_infer(const uint16_t* w, const float* feat, const float* blocks, int64_t units, float* minv,
-                            hipStream_t st) {
+hipError_t launch_mlp_infer(const uint16_t* w, const float* norm, float q_fallback, const float* feat,
+                            const float* blocks, int64_t units, float* minv, hipStream_t st) {
     const int64_t tiles = (units + TU - 1) / TU;
     int64_t g = (tiles + kInferWaves - 1) / kInferWaves;
     if (g > 4096) g = 4096;
     if (g < 1) g = 1;
-    hipLaunchKernelGGL(k_mlp_infer, dim3((unsigned)g), dim3(64 * kInferWaves), 0, st, w, feat, blocks, units, minv);
+    hipLaunchKernelGGL(k_mlp_infer, dim3((unsigned)g), dim3(64 * kInferWaves), 0, st, w, norm, q_fallback, feat, blocks,
+                       units, minv);
     return hipGetLastError();
 }
 
-hipError_t launch_mlp_train(float* w32, uint16_t* wbf, float* m, float* v, int t, float lr, float damp, const float* feat,
-                            const float* blocks, int n, float* loss, float* grad, hipStream_t st) {
+hipError_t launch_mlp_train(float* w32, uint16_t* wbf, float* m, float* v, int t, float lr, float damp,
+                            const float* norm, const float* feat, const float* blocks, int n, float* loss, float* grad,
+                            hipStream_t st) {
     hipLaunchKernelGGL(k_zero1, dim3(1), dim3(64), 0, st, loss, 1);
     if (n > 0) {
-        hipLaunchKernelGGL(k_mlp_train, dim3((unsigned)((n + TU - 1) / TU)), dim3(64), 0, st, wbf, feat, blocks, n,
-                           1.0f / (float)n, damp, grad, loss);
+        hipLaunchKernelGGL(k_mlp_train, dim3((unsigned)((n + TU - 1) / TU)), dim3(64), 0, st, wbf, norm, feat, blocks,
+                           n, 1.0f / (float)n, damp, grad, loss);
     }
     hipLaunchKernelGGL(k_adam, dim3((NW + 255) / 256), dim3(256), 0, st, w32, wbf, m, v, grad, t, lr);
+    return hipGetLastError();
+}
+
+hipError_t launch_feature_stats(const float* feat, int64_t n, float* norm, hipStream_t st) {
+    hipLaunchKernelGGL(k_feature_stats, dim3(NIN), dim3(kStatsBlock), 0, st, feat, n, norm);
     return hipGetLastError();
 }
 

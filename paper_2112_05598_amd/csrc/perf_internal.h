@@ -62,7 +62,7 @@ enum IFlag { I_DONE = 0, I_ITERS = 1, I_FLAGS = 2, I_NONFINITE = 3, I_COUNT = 16
 // Workspace layout (offsets in bytes from the workspace base).
 struct Layout {
     size_t cams, partials, scalars, hist, iflags;
-    size_t vr, vz, vp, vAp, vdelta, vxt, blocks, minv, xb16, feat, mlpw, footprint;
+    size_t vr, vz, vp, vAp, vdelta, vxt, blocks, minv, xb16, feat, mlpw, mlpnorm, footprint;
     size_t total;
     int64_t n_partials;
 };
@@ -116,12 +116,17 @@ hipError_t launch_pack_bf16(const float* in, uint16_t* out, int64_t n, hipStream
 hipError_t launch_check_finite(const float* p, int64_t n, int* flag, hipStream_t st);
 hipError_t launch_features_finalize(const void* x, int x_dtype, const float* sums, const float* blocks,
                                     int64_t units, float* feat, hipStream_t st);
+// counts: kVecGrid + 1 int64 of scratch; counts[kVecGrid] receives the number of kept rows
+hipError_t launch_training_rows(const float* feat, const float* blocks, int64_t units, unsigned seed, float keep,
+                                float* feat_out, float* blocks_out, int64_t cap, long long* counts, hipStream_t st);
 
 // ---------------------------------------------------------------- launchers (mlp.hip)
-hipError_t launch_mlp_infer(const uint16_t* w, const float* feat, const float* blocks, int64_t units, float* minv,
+hipError_t launch_mlp_infer(const uint16_t* w, const float* norm, float q_fallback, const float* feat,
+                            const float* blocks, int64_t units, float* minv, hipStream_t st);
+hipError_t launch_mlp_train(float* w32, uint16_t* wbf, float* m, float* v, int t, float lr, float damp,
+                            const float* norm, const float* feat, const float* blocks, int n, float* loss, float* grad,
                             hipStream_t st);
-hipError_t launch_mlp_train(float* w32, uint16_t* wbf, float* m, float* v, int t, float lr, float damp, const float* feat,
-                            const float* blocks, int n, float* loss, float* grad, hipStream_t st);
+hipError_t launch_feature_stats(const float* feat, int64_t n, float* norm, hipStream_t st);
 
 hipError_t launch_upsample(const float* src, int sx, int sy, int sz, int sw, int sh, float* dst, int dx, int dy,
                            int dz, int dw, int dh, int layers, float sigma_scale, hipStream_t st);

@@ -72,7 +72,8 @@ __device__ __forceinline__ double dot4(float4 a, float4 b) {
 //            z_c = y_c - e~ z_sigma, then z = D^-1/2 z.  Elimination keeps the FP32 rounding
 //            error along the block's own near-null direction; multiplying by the explicit
 //            inverse, whose entries reach 1/s, would spread it over every direction.
-//   Learned  (t_d, t_f, L row by row): z = D^-1/2 L (L^T (D^-1/2 r)).
+//   Learned  (t_d, t_f, L row by row): z = D^-1/2 L (L^T (D^-1/2 r)); a unit on the exact-block
+//            fallback holds the block form (-t_d, t_f, e~, 1/s) instead, told apart by t_d < 0.
 template <int KIND>
 __device__ __forceinline__ float4 precond_apply(const float* __restrict__ minv, int64_t u, float4 r) {
     if constexpr (KIND == PERF_PRECOND_NONE) {
@@ -89,7 +90,15 @@ __device__ __forceinline__ float4 precond_apply(const float* __restrict__ minv, 
         return make_float4(td * (y0 - e0 * zs), td * (y1 - e1 * zs), td * (y2 - e2 * zs), tf * zs);
     } else {
         const float4* q = reinterpret_cast<const float4*>(minv) + 3 * u;
-        const float4 q0 = q[0], q1 = q[1], q2 = q[2];
+        const float4 q0 = q[0], q1 = q[1];
+        if (q0.x < 0.0f) {
+            // a unit on the exact-block fallback: the block form, with t_d stored negated
+            const float td = -q0.x, tf = q0.y, e0 = q0.z, e1 = q0.w, e2 = q1.x, is = q1.y;
+            const float y0 = td * r.x, y1 = td * r.y, y2 = td * r.z, y3 = tf * r.w;
+            const float zs = (y3 - (e0 * y0 + e1 * y1 + e2 * y2)) * is;
+            return make_float4(td * (y0 - e0 * zs), td * (y1 - e1 * zs), td * (y2 - e2 * zs), tf * zs);
+        }
+        const float4 q2 = q[2];
         const float td = q0.x, tf = q0.y;
         const float l00 = q0.z, l10 = q0.w, l11 = q1.x, l20 = q1.y, l21 = q1.z, l22 = q1.w, l30 = q2.x, l31 = q2.y,
                     l32 = q2.z, l33 = q2.w;
@@ -368,6 +377,91 @@ __global__ void k_features(const void* __restrict__ xp, int x_bf16, const float*
     }
 }
 
+// Training rows of the learned preconditioner: every unit some ray touches (max(d, f) > 0) is
+// kept with probability keep, decided by a counter-based hash of (seed, unit), and the kept
+// rows are packed in unit order.  Workgroup g of a fixed grid owns one contiguous chunk of
+// units: it counts its kept rows, one workgroup turns the counts into offsets, and each
+// workgroup then writes its rows at its offset in order (deterministic output).
+__device__ __forceinline__ unsigned mix32(unsigned h) {
+    h ^= h >> 16;
+    h *= 0x85ebca6bu;
+    h ^= h >> 13;
+    h *= 0xc2b2ae35u;
+    h ^= h >> 16;
+    return h;
+}
+__device__ __forceinline__ bool keep_row(const float* __restrict__ blocks, int64_t u, unsigned seed, unsigned thresh) {
+    const float* b = blocks + 5 * u;
+    return fmaxf(b[0], b[4]) > 0.0f && mix32(seed ^ mix32((unsigned)u ^ (unsigned)(u >> 32) * 0x9e3779b9u)) < thresh;
+}
+
+// kept rows of the workgroup's chunk before each thread's unit in this pass of the chunk
+__device__ __forceinline__ int block_exclusive_count(bool flag, int* total) {
+    __shared__ int wsum[kVecBlock / 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const unsigned long long bal = __ballot(flag);
+    const int before_in_wave = __popcll(bal & ((1ull << lane) - 1ull));
+    if (lane == 0) wsum[wave] = __popcll(bal);
+    __syncthreads();
+    int before = before_in_wave, all = 0;
+#pragma unroll
+    for (int i = 0; i < kVecBlock / 64; ++i) {
+        before += (i < wave) ? wsum[i] : 0;
+        all += wsum[i];
+    }
+    __syncthreads();
+    *total = all;
+    return before;
+}
+
+__global__ __launch_bounds__(kVecBlock) void k_rows_count(const float* __restrict__ blocks, int64_t units,
+                                                          int64_t chunk, unsigned seed, unsigned thresh,
+                                                          long long* counts) {
+    const int64_t lo = blockIdx.x * chunk, hi = min(lo + chunk, units);
+    long long c = 0;
+    for (int64_t base = lo; base < hi; base += kVecBlock) {
+        const int64_t u = base + threadIdx.x;
+        int total;
+        (void)block_exclusive_count(u < hi && keep_row(blocks, u, seed, thresh), &total);
+        c += total;
+    }
+    if (threadIdx.x == 0) counts[blockIdx.x] = c;
+}
+
+__global__ void k_rows_offsets(long long* counts, int nb) {
+    if (threadIdx.x == 0) {
+        long long run = 0;
+        for (int i = 0; i < nb; ++i) {
+            const long long c = counts[i];
+            counts[i] = run;
+            run += c;
+        }
+        counts[nb] = run;
+    }
+}
+
+__global__ __launch_bounds__(kVecBlock) void k_rows_write(const float* __restrict__ feat, const float* __restrict__ blocks,
+                                                          int64_t units, int64_t chunk, unsigned seed, unsigned thresh,
+                                                          const long long* offsets, int64_t cap,
+                                                          float* __restrict__ feat_out, float* __restrict__ blocks_out) {
+    const int64_t lo = blockIdx.x * chunk, hi = min(lo + chunk, units);
+    long long at = offsets[blockIdx.x];
+    for (int64_t base = lo; base < hi; base += kVecBlock) {
+        const int64_t u = base + threadIdx.x;
+        const bool k = u < hi && keep_row(blocks, u, seed, thresh);
+        int total;
+        const int before = block_exclusive_count(k, &total);
+        const long long dst = at + before;
+        if (k && dst < cap) {
+#pragma unroll
+            for (int i = 0; i < 12; ++i) feat_out[12 * dst + i] = feat[12 * u + i];
+#pragma unroll
+            for (int i = 0; i < 5; ++i) blocks_out[5 * dst + i] = blocks[5 * u + i];
+        }
+        at += total;
+    }
+}
+
 unsigned grid_for(int64_t n) {
     int64_t g = (n + kVecBlock - 1) / kVecBlock;
     if (g > kVecGrid) g = kVecGrid;
@@ -493,6 +587,19 @@ hipError_t launch_pack_bf16(const float* in, uint16_t* out, int64_t n, hipStream
 hipError_t launch_check_finite(const float* p, int64_t n, int* flag, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_check_finite, dim3(grid_for(n)), dim3(kVecBlock), 0, st, p, n, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_training_rows(const float* feat, const float* blocks, int64_t units, unsigned seed, float keep,
+                                float* feat_out, float* blocks_out, int64_t cap, long long* counts, hipStream_t st) {
+    const int nb = kVecGrid;
+    const int64_t chunk = (units + nb - 1) / nb;
+    const double t = fmin(fmax((double)keep, 0.0), 1.0) * 4294967296.0;
+    const unsigned thresh = t >= 4294967295.0 ? 0xffffffffu : (unsigned)t;
+    hipLaunchKernelGGL(k_rows_count, dim3(nb), dim3(kVecBlock), 0, st, blocks, units, chunk, seed, thresh, counts);
+    hipLaunchKernelGGL(k_rows_offsets, dim3(1), dim3(64), 0, st, counts, nb);
+    hipLaunchKernelGGL(k_rows_write, dim3(nb), dim3(kVecBlock), 0, st, feat, blocks, units, chunk, seed, thresh, counts,
+                       cap, feat_out, blocks_out);
     return hipGetLastError();
 }
 

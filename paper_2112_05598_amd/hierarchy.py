@@ -53,7 +53,7 @@ def gn_hierarchy(spec, cams, targets: torch.Tensor, x0: torch.Tensor, levels: in
             x = upsample(specs[k - 1], x, sp)
         sc = Scene(sp, cams, targets, learned=precond == "learned", device=str(targets.device))
         if precond == "learned":
-            sc.mlp_set_weights(weights)
+            weights.install(sc)
         for _ in range(steps[k]):
             if jitter_base:
                 sc.set_jitter(jitter_base + len(recs))
@@ -93,8 +93,8 @@ def main():
     ref.set_targets(targets)
     weights = None
     if args.precond == "learned":
-        from .learned import load_weights
-        weights = load_weights(device="cuda:0")
+        from .learned import load_model
+        weights = load_model(device="cuda:0")
     # flat: the finest level only, from the initial guess
     x = torch.from_numpy(w.x_init).to(dev)
     torch.cuda.synchronize()

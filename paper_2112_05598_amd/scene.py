@@ -204,12 +204,33 @@ class Scene:
         abi.check(self.lib.perf_precond_features(self.handle, _ptr(x), _ptr(feat), _ptr(blocks)))
         return feat.view(-1, 12), blocks.view(-1, 5)
 
-    def mlp_set_weights(self, w_bf16: torch.Tensor):
+    def mlp_set_weights(self, w_bf16: torch.Tensor, norm: torch.Tensor, q_fallback: float = float("inf")):
+        """Network weights (bfloat16 [PERF_MLP_NW]), standardisation (float32 [PERF_MLP_NNORM]) and
+        the per-unit fallback threshold on q = ||L L^T B~ - I||_F^2 (inf: never)."""
         if w_bf16.dtype != torch.bfloat16 or w_bf16.numel() != abi.PERF_MLP_NW or w_bf16.device != self.device:
             raise ValueError("weights must be a bfloat16 tensor of PERF_MLP_NW elements on the scene's device")
+        if norm.dtype != torch.float32 or norm.numel() != abi.PERF_MLP_NNORM or norm.device != self.device:
+            raise ValueError("norm must be a float32 tensor of PERF_MLP_NNORM elements on the scene's device")
         self._bind()
         self._mlp_w = w_bf16.contiguous()
-        abi.check(self.lib.perf_mlp_set_weights(self.handle, _ptr(self._mlp_w), abi.PERF_MLP_NW))
+        self._mlp_norm = norm.contiguous()
+        abi.check(self.lib.perf_mlp_set_weights(self.handle, _ptr(self._mlp_w), abi.PERF_MLP_NW, _ptr(self._mlp_norm),
+                                                ctypes.c_float(q_fallback)))
+
+    def training_rows(self, feat: torch.Tensor, blocks: torch.Tensor, seed: int, keep: float, cap: int):
+        """(features [k, 12], blocks [k, 5], n_kept) for a random subset of the touched units
+        (library-side sampling: each kept with probability keep; at most cap rows written, unit
+        order; cap = 0 only counts)."""
+        self._bind()
+        fo = torch.empty(max(cap, 1) * 12, dtype=torch.float32, device=self.device)
+        bo = torch.empty(max(cap, 1) * 5, dtype=torch.float32, device=self.device)
+        n = ctypes.c_int64()
+        abi.check(self.lib.perf_mlp_training_rows(self.handle, _ptr(feat.contiguous()), _ptr(blocks.contiguous()),
+                                                  ctypes.c_uint32(int(seed) & 0xFFFFFFFF), ctypes.c_float(keep),
+                                                  _ptr(fo) if cap else None, _ptr(bo) if cap else None, cap,
+                                                  ctypes.byref(n)))
+        k = min(n.value, cap)
+        return fo.view(-1, 12)[:k], bo.view(-1, 5)[:k], n.value
 
     def mlp_infer(self, feat: torch.Tensor, blocks: torch.Tensor):
         """[units, 12] predicted block inverses in scaled form (t_d, t_f, L row by row)."""
@@ -237,14 +258,27 @@ class Scene:
                     beta=list(st.beta[:max(k - 1, 0)]), pAp=list(st.pAp[:k + 1]), ms_phase=list(st.ms_phase[:6]), ms_jtj=st.ms_phase[6], n_jtj=int(st.ms_phase[7]))
 
 
-def mlp_train_step(w32, wbf16, m, v, t: int, lr: float, feat, blocks, loss, grad, stream=None, damp: float = 0.0):
-    """One Adam step of the learned preconditioner on a batch (feat [n,12], blocks [n,5]);
-    the target is the damped normalised inverse (B~ + damp I)^-1."""
+def mlp_train_step(w32, wbf16, m, v, t: int, lr: float, norm, feat, blocks, loss, grad, stream=None,
+                   damp: float = 0.0):
+    """One Adam step of the learned preconditioner on a batch (feat [n,12], blocks [n,5]) with the
+    fixed standardisation norm [32]; the target is the damped normalised inverse (B~ + damp I)^-1."""
     lib = abi.load()
     n = int(feat.shape[0])
     st = ctypes.c_void_p(torch.cuda.current_stream(feat.device).cuda_stream) if stream is None else stream
-    abi.check(lib.perf_mlp_train_step(_ptr(w32), _ptr(wbf16), _ptr(m), _ptr(v), int(t), ctypes.c_float(lr), ctypes.c_float(damp),
-                                      _ptr(feat), _ptr(blocks), n, _ptr(loss), _ptr(grad), st))
+    abi.check(lib.perf_mlp_train_step(_ptr(w32), _ptr(wbf16), _ptr(m), _ptr(v), int(t), ctypes.c_float(lr),
+                                      ctypes.c_float(damp), _ptr(norm), _ptr(feat), _ptr(blocks), n, _ptr(loss),
+                                      _ptr(grad), st))
+
+
+def mlp_feature_stats(feat: torch.Tensor, stream=None) -> torch.Tensor:
+    """Standardisation [32] = (mu[16], s[16]) of a training set of features [n, 12] (library-side)."""
+    lib = abi.load()
+    if feat.dtype != torch.float32 or not feat.is_cuda or feat.dim() != 2 or feat.shape[1] != 12:
+        raise ValueError("features must be a float32 device tensor of shape [n, 12]")
+    out = torch.empty(abi.PERF_MLP_NNORM, dtype=torch.float32, device=feat.device)
+    st = ctypes.c_void_p(torch.cuda.current_stream(feat.device).cuda_stream) if stream is None else stream
+    abi.check(lib.perf_mlp_feature_stats(_ptr(feat.contiguous()), feat.shape[0], _ptr(out), st))
+    return out
 
 
 def upsample(spec_from, x_from: torch.Tensor, spec_to, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:

@@ -55,6 +55,52 @@ def test_features_match_oracle(setup):
         assert rel(feat[live, c], f_or[live, c]) <= 1e-4, c
 
 
+def gpu_norm(feat):
+    """The library's standardisation of the features (and its FP64 copy)."""
+    from paper_2112_05598_amd.scene import mlp_feature_stats
+    norm = mlp_feature_stats(feat)
+    return norm, norm.cpu().numpy().astype(np.float64)
+
+
+def test_feature_stats_match_oracle(setup):
+    from oracle import mlp
+    w, orc, sc, targets, t, x = setup
+    feat, blocks = sc.features(torch.from_numpy(x).cuda())
+    live = torch.nonzero(torch.maximum(blocks[:, 0], blocks[:, 4]) > 0).squeeze(1)
+    f = feat[live].contiguous()
+    _, n64 = gpu_norm(f)
+    ref = mlp.feature_stats(f.cpu().numpy().astype(np.float64))
+    np.testing.assert_allclose(n64[:12], ref[:12], rtol=1e-6, atol=1e-6)
+    np.testing.assert_allclose(n64[16:28], ref[16:28], rtol=1e-5)
+    assert np.all(n64[12:16] == 0) and np.all(n64[28:] == 0)
+
+
+def test_training_rows_are_the_touched_units(setup):
+    """keep = 1: every touched unit, in unit order, bit for bit; keep = 0.3: a deterministic
+    subset in unit order of about 30 % of them."""
+    w, orc, sc, targets, t, x = setup
+    feat, blocks = sc.features(torch.from_numpy(x).cuda())
+    b = blocks.cpu().numpy()
+    f = feat.cpu().numpy()
+    touched = np.nonzero(np.maximum(b[:, 0], b[:, 4]) > 0)[0]
+    fo, bo, n = sc.training_rows(feat, blocks, 5, 1.0, len(touched) + 10)
+    assert n == len(touched)
+    np.testing.assert_array_equal(fo.cpu().numpy(), f[touched])
+    np.testing.assert_array_equal(bo.cpu().numpy(), b[touched])
+    fo1, bo1, n1 = sc.training_rows(feat, blocks, 9, 0.3, len(touched))
+    fo2, bo2, n2 = sc.training_rows(feat, blocks, 9, 0.3, len(touched))
+    assert n1 == n2 and torch.equal(fo1, fo2) and torch.equal(bo1, bo2)
+    sd = np.sqrt(len(touched) * 0.3 * 0.7)
+    assert abs(n1 - 0.3 * len(touched)) <= 5 * sd + 1
+    # a subset of the touched units' rows, in unit order
+    key = {tuple(r): i for i, r in enumerate(np.concatenate([f[touched], b[touched]], 1).tolist())}
+    idx = [key[tuple(r)] for r in np.concatenate([fo1.cpu().numpy(), bo1.cpu().numpy()], 1).tolist()]
+    assert np.all(np.diff(idx) > 0)
+    # a cap below the count writes the first cap rows of the same selection
+    fo3, _, n3 = sc.training_rows(feat, blocks, 9, 0.3, 17)
+    assert n3 == n1 and torch.equal(fo3, fo1[:17])
+
+
 def test_mlp_inference_matches_fp64_mlp(setup):
     from oracle import mlp
     w, orc, sc, targets, t, x = setup
@@ -64,8 +110,9 @@ def test_mlp_inference_matches_fp64_mlp(setup):
     bits = mlp.bf16_bits(mlp.pack(p))
     wq = mlp.bits_to_f64(bits)
     wt = torch.from_numpy(bits.view(np.int16)).cuda().view(torch.bfloat16)
-    sc.mlp_set_weights(wt)
     feat, blocks = sc.features(torch.from_numpy(x).cuda())
+    norm, n64 = gpu_norm(feat)
+    sc.mlp_set_weights(wt, norm)
     out = sc.mlp_infer(feat, blocks).cpu().numpy()
     f64, b64 = feat.cpu().numpy().astype(np.float64), blocks.cpu().numpy().astype(np.float64)
     iu = np.triu_indices(4)
@@ -78,8 +125,8 @@ def test_mlp_inference_matches_fp64_mlp(setup):
     L = learned_factor(out)
     got = (L @ np.transpose(L, (0, 2, 1)))[:, iu[0], iu[1]]
     scale = np.where(live[:, None], 1.0 / (dis[:, iu[0]] * dis[:, iu[1]] + 1e-300), 0.0)
-    emu = mlp.minv(wq, f64, b64, emulate_bf16=True)[:, iu[0], iu[1]] * scale
-    exact = mlp.minv(wq, f64, b64)[:, iu[0], iu[1]] * scale
+    emu = mlp.minv(wq, n64, f64, b64, emulate_bf16=True)[:, iu[0], iu[1]] * scale
+    exact = mlp.minv(wq, n64, f64, b64)[:, iu[0], iu[1]] * scale
     # same bf16 roundings of inputs and activations: FP32 accumulation and rare ties only
     assert rel(got[live], emu[live]) <= 2e-3
     # against the all-FP64 network: three bf16 roundings (unit roundoff 2^-9) per path
@@ -107,10 +154,12 @@ def test_mlp_training_gradient(setup, damp):
     wbf = torch.from_numpy(bits.view(np.int16)).to(dev).view(torch.bfloat16).clone()
     m = torch.zeros_like(w32); v = torch.zeros_like(w32); g = torch.zeros_like(w32)
     loss = torch.zeros(1, dtype=torch.float32, device=dev)
-    mlp_train_step(w32, wbf, m, v, 1, 1e-4, fb, bb, loss, g, damp=damp)
+    norm, n64 = gpu_norm(fb)
+    mlp_train_step(w32, wbf, m, v, 1, 1e-4, norm, fb, bb, loss, g, damp=damp)
     torch.cuda.synchronize()
     grad_gpu = (m / 0.1).cpu().numpy()  # first Adam step from m = 0: m = (1 - beta1) g
-    L_or, g_or = mlp.loss_and_grad(wq, fb.cpu().numpy().astype(np.float64), bb.cpu().numpy().astype(np.float64), damp)
+    L_or, g_or = mlp.loss_and_grad(wq, n64, fb.cpu().numpy().astype(np.float64), bb.cpu().numpy().astype(np.float64),
+                                   damp)
     assert abs(loss.item() - L_or) <= 2e-2 * L_or
     cos = grad_gpu @ g_or / (np.linalg.norm(grad_gpu) * np.linalg.norm(g_or))
     assert cos >= 0.999
@@ -143,13 +192,14 @@ def test_learned_gn_step_matches_oracle(setup):
     from gpu_checks import check_pcg_history
     w, orc, sc, targets, t, x = setup
     bits, wq = learned_weights(7)
-    sc.mlp_set_weights(torch.from_numpy(bits.view(np.int16)).cuda().view(torch.bfloat16))
     tx = torch.from_numpy(x).cuda()
     feat, blocks = sc.features(tx)
+    norm, n64 = gpu_norm(feat)
+    sc.mlp_set_weights(torch.from_numpy(bits.view(np.int16)).cuda().view(torch.bfloat16), norm)
     minv_gpu = learned_minv(sc.mlp_infer(feat, blocks).cpu().numpy())
     x64 = x.astype(np.float64)
     _, b_or, _ = orc.grad_blocks(x64, targets)
-    minv_or = mlp.minv(wq, feat.cpu().numpy().astype(np.float64), b_or, emulate_bf16=True)
+    minv_or = mlp.minv(wq, n64, feat.cpu().numpy().astype(np.float64), b_or, emulate_bf16=True)
     st = sc.gn_step(tx.clone(), max_iters=8, precond="learned")
     assert st["F_after"] < st["F_before"]
     assert st["pcg_iters"] >= 1 and not (st["flags"] & 1)
@@ -159,3 +209,38 @@ def test_learned_gn_step_matches_oracle(setup):
         assert st["pcg_iters"] == ref["pcg"].iters
         check_pcg_history(st, ref["pcg"], min(5, ref["pcg"].iters), tol=tol)
         assert abs(st["F_after"] - ref["F_after"]) <= 1e-3 * ref["F_before"], (st["F_after"], ref["F_after"])
+
+
+def test_fallback_units_take_the_exact_block_inverse(setup):
+    """Threshold 0: every touched unit takes the exact block inverse (the block form with t_d
+    negated), equal to the oracle's (B + rho I)^-1; a finite threshold: units the FP64 network
+    places clearly above it fall back, clearly below it keep the prediction, both on the GPU."""
+    import oracle
+    from oracle import mlp
+    from gpu_checks import block_minv
+    w, orc, sc, targets, t, x = setup
+    bits, wq = learned_weights(3)
+    wt = torch.from_numpy(bits.view(np.int16)).cuda().view(torch.bfloat16)
+    feat, blocks = sc.features(torch.from_numpy(x).cuda())
+    norm, n64 = gpu_norm(feat)
+    b64 = blocks.cpu().numpy().astype(np.float64)
+    live = np.maximum(b64[:, 0], b64[:, 4]) > 0
+    sc.mlp_set_weights(wt, norm, 0.0)
+    out = sc.mlp_infer(feat, blocks).cpu().numpy()
+    assert np.all(out[live, 0] < 0) and np.all(out[~live] == 0)
+    blk = out[:, :8].copy()
+    blk[:, 0] = -blk[:, 0]
+    got = block_minv(blk)
+    ref = oracle.block_inverse(b64)
+    scale = np.abs(ref).max(axis=(1, 2))
+    err = np.abs(got - ref).max(axis=(1, 2))[live] / scale[live]
+    assert err.max() <= 1e-5, err.max()
+    _, fb, q = mlp.minv(wq, n64, feat.cpu().numpy().astype(np.float64), b64, emulate_bf16=True, q_fallback=0.0,
+                        return_fallback=True)
+    thr = float(np.median(q[live]))
+    sc.mlp_set_weights(wt, norm, thr)
+    out = sc.mlp_infer(feat, blocks).cpu().numpy()
+    clear_hi = live & (q > 1.05 * thr)
+    clear_lo = live & (q < 0.95 * thr)
+    assert clear_hi.sum() > 10 and clear_lo.sum() > 10
+    assert np.all(out[clear_hi, 0] < 0) and np.all(out[clear_lo, 0] > 0)

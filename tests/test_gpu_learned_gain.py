@@ -14,8 +14,8 @@ def test_learned_reaches_jacobi_objective_sooner():
     from paper_2112_05598_amd import learned
     print("[case] learned vs Jacobi GN, held-out seed 20005", flush=True)
     w = ps.workload("cfg4", seed=20005)
-    wbf = learned.load_weights(device="cuda:0")
-    out = learned.gn_compare(w, {"learned": wbf}, n_steps=5, pcg_iters=30, extra_steps=3,
+    model = learned.load_model(device="cuda:0")
+    out = learned.gn_compare(w, {"learned": model}, n_steps=5, pcg_iters=30, extra_steps=3,
                              log=lambda m: print(m, flush=True))
     jac, lrn = out["jacobi"], out["learned"]
     assert jac["F"][-1] < jac["F0"]

@@ -11,6 +11,13 @@ def mlp(oracle_mod):
     return mlp
 
 
+def unit_norm(mlp):
+    """Standardisation that leaves features within the clamp unchanged (mu = 0, s = 1)."""
+    norm = np.zeros(2 * mlp.N_IN_PAD)
+    norm[mlp.N_IN_PAD:mlp.N_IN_PAD + mlp.N_IN] = 1.0
+    return norm
+
+
 def random_blocks(n, seed):
     rng = np.random.default_rng(seed)
     d = rng.uniform(0.1, 5.0, n)
@@ -26,7 +33,7 @@ def random_blocks(n, seed):
 
 def unit_errors(mlp, w, feat, blocks, damp):
     """||L L^T (B~ + damp I) - I||_F^2 per unit, assembled independently of loss_and_grad."""
-    L = mlp.factor(mlp.forward(w, feat)[0])
+    L = mlp.factor(mlp.forward(w, unit_norm(mlp), feat)[0])
     Bn, _, live = mlp.normalised_block(blocks)
     E = L @ np.transpose(L, (0, 2, 1)) @ (Bn + damp * np.eye(4)) - np.eye(4)
     q = (E * E).sum(axis=(1, 2))
@@ -43,7 +50,8 @@ def test_loss_gradient_matches_finite_differences(mlp, damp):
     q = unit_errors(mlp, w, feat, blocks, damp)
     # both branches of the robust loss are exercised
     assert np.any(q > mlp.KAPPA) and np.any((q > 0) & (q < mlp.KAPPA))
-    loss, g = mlp.loss_and_grad(w, feat, blocks, damp)
+    norm = unit_norm(mlp)
+    loss, g = mlp.loss_and_grad(w, norm, feat, blocks, damp)
     expect = np.where(q > mlp.KAPPA, 4.0 * np.sqrt(q) - 4.0, q).sum() / 40
     assert abs(loss - expect) <= 1e-12 * expect
     idx = rng.choice(mlp.NW, 60, replace=False)
@@ -51,7 +59,8 @@ def test_loss_gradient_matches_finite_differences(mlp, damp):
     for i in idx:
         wp = w.copy(); wp[i] += eps
         wm = w.copy(); wm[i] -= eps
-        fd = (mlp.loss_and_grad(wp, feat, blocks, damp)[0] - mlp.loss_and_grad(wm, feat, blocks, damp)[0]) / (2 * eps)
+        fd = (mlp.loss_and_grad(wp, norm, feat, blocks, damp)[0]
+              - mlp.loss_and_grad(wm, norm, feat, blocks, damp)[0]) / (2 * eps)
         assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(fd)), (i, fd, g[i])
 
 
@@ -79,7 +88,7 @@ def test_damped_inverse_is_a_zero_of_the_loss(mlp, damp):
         p["W3"][:] = 0.0
         p["b3"][:] = 0.0
         p["b3"][:10] = mlp.raw_from_factor(L[u:u + 1])[0]
-        loss, g = mlp.loss_and_grad(mlp.pack(p), np.zeros((1, 12)), blocks[u:u + 1], damp)
+        loss, g = mlp.loss_and_grad(mlp.pack(p), unit_norm(mlp), np.zeros((1, 12)), blocks[u:u + 1], damp)
         assert loss < 1e-20
         assert np.abs(g).max() < 1e-9
 
@@ -110,7 +119,7 @@ def test_initial_network_is_jacobi(mlp, oracle_mod):
     w = mlp.pack(p)
     blocks = random_blocks(20, 6)
     feat = np.random.default_rng(1).normal(size=(20, 12))
-    M = mlp.minv(w, feat, blocks)
+    M = mlp.minv(w, unit_norm(mlp), feat, blocks)
     sp = np.logaddexp(0.0, 0.5413)
     b = blocks
     rho = 1e-6 * np.maximum(b[:, 0], b[:, 4])
@@ -155,9 +164,9 @@ def test_learned_inverse_scales_with_the_block(mlp):
     w = mlp.init_weights(5)
     blocks = random_blocks(6, 8)
     feat = np.random.default_rng(2).normal(size=(6, 12))
-    M1 = mlp.minv(w, feat, blocks)
+    M1 = mlp.minv(w, unit_norm(mlp), feat, blocks)
     for s in (1e-20, 1e-41):
-        Ms = mlp.minv(w, feat, blocks * s)
+        Ms = mlp.minv(w, unit_norm(mlp), feat, blocks * s)
         np.testing.assert_allclose(Ms * s, M1, rtol=1e-12, atol=0)
     # units no ray touches get 0; the others are symmetric positive definite
     assert np.all(M1[:3] == 0)
@@ -207,3 +216,56 @@ def test_feature_sums_axis_ray_closed_form(oracle_mod):
     assert np.all(vox[mask] == 0.0)
     tex = sums[spec.n_vox:].sum(0)
     np.testing.assert_allclose(tex, [1.0, T_end, *(T_end * np.array(spec.background)), ae], rtol=1e-12)
+
+
+def test_feature_stats_closed_form(mlp):
+    """Column i = a_i + b_i t with t = +-1 alternating: mean a_i, population std |b_i|; a
+    constant column gets s = 1 / 1e-3; the padding stays 0."""
+    a = np.linspace(-20.0, 5.0, 12)
+    b = np.linspace(0.5, 3.0, 12)
+    b[7] = 0.0
+    t = np.tile([1.0, -1.0], 50)
+    feat = a[None, :] + b[None, :] * t[:, None]
+    norm = mlp.feature_stats(feat)
+    np.testing.assert_allclose(norm[:12], a, rtol=1e-14, atol=1e-13)
+    want = 1.0 / np.maximum(np.abs(b), 1e-3)
+    np.testing.assert_allclose(norm[16:28], want, rtol=1e-12)
+    assert np.all(norm[12:16] == 0) and np.all(norm[28:32] == 0)
+
+
+def test_standardise_centres_scales_and_clamps(mlp):
+    rng = np.random.default_rng(3)
+    feat = rng.normal(size=(200, 12)) * 4.0 + 10.0
+    norm = mlp.feature_stats(feat)
+    x = mlp.standardise(norm, feat)
+    inner = np.abs(x[:, :12]) < mlp.CLAMP
+    z = (feat - feat.mean(0)) / feat.std(0)
+    np.testing.assert_allclose(x[:, :12][inner], z[inner], rtol=1e-12)
+    far = feat.copy(); far[0, 3] = 1e6; far[1, 5] = -1e6
+    xf = mlp.standardise(norm, far)
+    assert xf[0, 3] == mlp.CLAMP and xf[1, 5] == -mlp.CLAMP
+    assert np.all(x[:, 12:] == 0)
+
+
+def test_fallback_units_take_the_exact_block_inverse(mlp, oracle_mod):
+    """Units whose prediction error q exceeds the threshold get (B + rho I)^-1 exactly, the
+    others keep D^-1/2 L L^T D^-1/2; a threshold of 0 turns the whole preconditioner into
+    plain block-Jacobi, an infinite one never falls back."""
+    rng = np.random.default_rng(11)
+    w = mlp.init_weights(4) + 0.2 * rng.normal(size=mlp.NW)
+    blocks = random_blocks(60, 5)
+    feat = rng.normal(size=(60, 12))
+    norm = unit_norm(mlp)
+    M_all, fb_all, q = mlp.minv(w, norm, feat, blocks, q_fallback=0.0, return_fallback=True)
+    np.testing.assert_allclose(M_all, oracle_mod.block_inverse(blocks), rtol=1e-9, atol=1e-12)
+    M_none, fb_none, _ = mlp.minv(w, norm, feat, blocks, return_fallback=True)
+    assert not fb_none.any()
+    thr = float(np.median(q[3:]))
+    M, fb, _ = mlp.minv(w, norm, feat, blocks, q_fallback=thr, return_fallback=True)
+    assert np.array_equal(fb, (q > thr) & (np.arange(60) >= 3))
+    np.testing.assert_array_equal(M[~fb], M_none[~fb])
+    np.testing.assert_allclose(M[fb], M_all[fb], rtol=1e-12)
+    # the error measure: the exact inverse scores 0
+    Bn, _, live = mlp.normalised_block(blocks)
+    Lx = np.linalg.cholesky(np.linalg.inv(Bn[live]))
+    assert mlp.prediction_error(Lx, Bn[live]).max() < 1e-18
