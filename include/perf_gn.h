@@ -257,7 +257,7 @@ int32_t perf_upsample(const perf_scene_desc* from, const float* d_from, const pe
  *           1 - |e~|^2 its Schur complement; M^-1 = (B + rho I)^-1 = D^-1/2 [[I3, e~], [e~^T, 1]]^-1
  *           D^-1/2, applied by elimination (z_sigma = (y_sigma - e~ . y_c) / s, z_c = y_c -
  *           e~ z_sigma on y = D^-1/2 r), which keeps FP32 rounding along the block's near-null
- *           direction; all 8 are 0 for an empty unit (max(d, f) = 0).
+ *           direction; all 8 are 0 for an empty unit (max(d, f) = 0, or a non-finite block).
  * Caller-owned device memory; asynchronous on stream.  PERF_EINVAL for a null pointer with
  * units > 0, units < 0 or another kind.
  */
@@ -288,12 +288,12 @@ int32_t perf_pack_bf16(const float* d_in, uint16_t* d_out, int64_t n, void* stre
  *   the diagonal); M^-1 = D^-1/2 L L^T D^-1/2 with D^-1/2 = diag(t_d, t_d, t_d, t_f) as in
  *   perf_invert_blocks (after the ridge), applied as D^-1/2 L (L^T (D^-1/2 r)); a unit on the
  *   fallback holds (-t_d, t_f, e~, 1/s, 0, ...) instead, the block form of perf_invert_blocks with
- *   t_d negated; units with max(d, f) = 0 get 0.
+ *   t_d negated; units with max(d, f) = 0 or a non-finite block get 0.
  * perf_mlp_train_step: one Adam step on a batch of n (feature, block) rows: per-unit error
  *   E = L L^T (Bn + damp I) - I with Bn = D^-1/2 B D^-1/2, so that the target is the damped
  *   normalised inverse (damp = 0: exact block-Jacobi; damp -> inf: Jacobi); the loss is the
  *   mean over the n rows of q = ||E||_F^2 where q <= 4 and 4 sqrt(q) - 4 above (robust against
- *   near-singular blocks); FP32 master weights d_w32 [PERF_MLP_NW], d_norm the fixed
+ *   near-singular blocks; rows with max(d, f) = 0 or a non-finite block count as 0); FP32 master weights d_w32 [PERF_MLP_NW], d_norm the fixed
  *   standardisation, Adam moments d_m, d_v [PERF_MLP_NW], step count t (>= 1), learning rate
  *   lr; writes the updated bf16 copy to d_wbf16 and the batch loss to d_loss (device
  *   float[1]).  d_grad_scratch [PERF_MLP_NW] FP32 accumulates the gradient; it must be zero on
@@ -301,7 +301,8 @@ int32_t perf_pack_bf16(const float* d_in, uint16_t* d_out, int64_t n, void* stre
  * perf_mlp_feature_stats: d_norm from n rows of features d_feat [n][12]: per-feature mean and
  *   s = 1 / max(std, 1e-3), std the population standard deviation, in FP64 and deterministic.
  * perf_mlp_training_rows: training rows from one traversal's features and blocks: every unit
- *   some ray touches (max(d, f) > 0) is kept with probability keep, decided by a hash of
+ *   some ray touches (max(d, f) > 0) whose features and block are finite is kept with
+ *   probability keep, decided by a hash of
  *   (seed, unit), and the kept rows are written to d_feat_out [cap][12] and d_blocks_out
  *   [cap][5] in unit order (deterministic); *n_kept (host) receives the number of kept rows,
  *   of which the first min(n_kept, cap) are written.  Synchronises.

@@ -316,14 +316,15 @@ RIDGE = 1e-6
 
 
 def block_inverse(blocks: np.ndarray, ridge: float = RIDGE) -> np.ndarray:
-    """Inverse of each 4x4 block after adding ridge*max(d, f) to the diagonal; 0 for empty units.
+    """Inverse of each 4x4 block after adding ridge*max(d, f) to the diagonal; 0 for empty units
+    (no ray: max(d, f) = 0; or a non-finite block).
 
     Returned as [units,4,4] (the plain matrix inverse, numpy.linalg.inv).
     """
     b = np.asarray(blocks, dtype=np.float64)
     B = block_matrix(b)
     m = np.maximum(b[:, 0], b[:, 4])
-    live = m > 0
+    live = (m > 0) & np.all(np.isfinite(b), axis=1)  # a non-finite block counts as an empty unit
     out = np.zeros_like(B)
     if np.any(live):
         Bl = B[live] + (ridge * m[live])[:, None, None] * np.eye(4)[None]

@@ -159,16 +159,16 @@ def normalised_block(blocks: np.ndarray):
     b = np.asarray(blocks, dtype=np.float64)
     d, e, f = b[:, 0], b[:, 1:4], b[:, 4]
     m = np.maximum(d, f)
-    live = m > 0
-    rho = RIDGE * m
+    live = (m > 0) & np.all(np.isfinite(b), axis=1)  # a non-finite block counts as an empty unit
+    rho = RIDGE * np.where(live, m, 0.0)
     dd, ff = d + rho, f + rho
     sd = np.where(live, 1.0 / np.sqrt(np.where(live, dd, 1.0)), 0.0)
     sf = np.where(live, 1.0 / np.sqrt(np.where(live, ff, 1.0)), 0.0)
     Bn = np.zeros((b.shape[0], 4, 4))
     for i in range(3):
         Bn[:, i, i] = np.where(live, 1.0, 0.0)
-        Bn[:, i, 3] = e[:, i] * sd * sf
-        Bn[:, 3, i] = e[:, i] * sd * sf
+        Bn[:, i, 3] = np.where(live, e[:, i] * sd * sf, 0.0)
+        Bn[:, 3, i] = np.where(live, e[:, i] * sd * sf, 0.0)
     Bn[:, 3, 3] = np.where(live, 1.0, 0.0)
     dis = np.stack([sd, sd, sd, sf], axis=1)
     return Bn, dis, live
@@ -189,7 +189,7 @@ def minv(w: np.ndarray, norm: np.ndarray, feat: np.ndarray, blocks: np.ndarray, 
     L = factor(raw)
     Bn, dis, live = normalised_block(blocks)
     q = prediction_error(L, Bn)
-    fb = live & (q > q_fallback)
+    fb = live & ~(q <= q_fallback)  # (a non-finite prediction falls back too)
     N = L @ np.transpose(L, (0, 2, 1))
     if np.any(fb):
         N[fb] = np.linalg.inv(Bn[fb])

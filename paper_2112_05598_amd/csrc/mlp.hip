@@ -222,7 +222,10 @@ __global__ __launch_bounds__(64 * kInferWaves) void k_mlp_infer(const unsigned s
             float4* o = reinterpret_cast<float4*>(minv) + 3 * unit;
             const float d = b[0], f = b[4];
             const float m = fmaxf(d, f);
-            if (!(m > 0.0f)) {
+            bool finite = true;
+#pragma unroll
+            for (int i = 0; i < 5; ++i) finite &= isfinite(b[i]);
+            if (!(m > 0.0f) || !finite) {  // no ray, or a non-finite block: an empty unit
                 o[0] = o[1] = o[2] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
             } else {
                 float raw[NO];
@@ -258,7 +261,7 @@ __global__ __launch_bounds__(64 * kInferWaves) void k_mlp_infer(const unsigned s
                     const float v3 = P[i][0] * e[0] + P[i][1] * e[1] + P[i][2] * e[2] + P[i][3] - (i == 3 ? 1.0f : 0.0f);
                     q += v3 * v3;
                 }
-                if (q > q_fallback) {
+                if (!(q <= q_fallback)) {  // (a non-finite prediction falls back too)
                     // the exact block inverse in the elimination form of the block preconditioner,
                     // marked by a negative t_d
                     const double is = 1.0 / (1.0 - (a0 * a0 + a1 * a1 + a2 * a2));
@@ -303,11 +306,15 @@ __global__ __launch_bounds__(64) void k_mlp_train(const unsigned short* __restri
         const float* b = blocks + 5 * unit;
         const float d = b[0], f = b[4];
         const float m = fmaxf(d, f);
-        if (m > 0.0f) {
-            const float rho = kRidge * m;
-            const float sd = 1.0f / sqrtf(d + rho), sf = 1.0f / sqrtf(f + rho);
-            // normalised block D^-1/2 (B + rho I) D^-1/2: unit diagonal, e / sqrt(d f) off it
-            const float e0 = b[1] * sd * sf, e1 = b[2] * sd * sf, e2 = b[3] * sd * sf;
+        bool finite = true;
+#pragma unroll
+        for (int i = 0; i < 5; ++i) finite &= isfinite(b[i]);
+        if (m > 0.0f && finite) {  // (a non-finite block contributes nothing)
+            // normalised block D^-1/2 (B + rho I) D^-1/2: unit diagonal, e / sqrt(d f) off it; in
+            // double, as in inference (the ridge of a block in the subnormal range underflows FP32)
+            const double rho = (double)kRidge * m;
+            const double sdf = 1.0 / sqrt(((double)d + rho) * ((double)f + rho));
+            const float e0 = (float)(b[1] * sdf), e1 = (float)(b[2] * sdf), e2 = (float)(b[3] * sdf);
             const float g1 = 1.0f + damp;
             const float Bn[4][4] = {{g1, 0.0f, 0.0f, e0}, {0.0f, g1, 0.0f, e1}, {0.0f, 0.0f, g1, e2},
                                     {e0, e1, e2, g1}};

@@ -35,22 +35,39 @@
 namespace perf {
 namespace {
 
-__device__ __forceinline__ float bf16_to_f32(unsigned short b) { return __uint_as_float(((unsigned)b) << 16); }
+// Loads of parameter and tangent vectors go through buffer resources: the voxel's byte offset is
+// one 32-bit VGPR and the trilinear corner's offset (a multiple of the row and slice pitch, the
+// same for every lane) an SGPR, so a corner costs one load and no 64-bit address arithmetic.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, unsigned bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+
+struct VecF4 {  // FP32 float4 per unit
+    __amdgpu_buffer_rsrc_t r;
+    static constexpr int kBytes = 16;
+    __device__ __forceinline__ float4 load(int voff, int soff) const {
+        const auto q = __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0);
+        return make_float4(__int_as_float((int)q[0]), __int_as_float((int)q[1]), __int_as_float((int)q[2]),
+                           __int_as_float((int)q[3]));
+    }
+    __device__ __forceinline__ float4 operator()(int i) const { return load(i * kBytes, 0); }
+};
 
 template <int PD>
 struct XL;
 template <>
-struct XL<PERF_F32> {
-    const float4* __restrict__ p;
-    __device__ __forceinline__ float4 operator()(int i) const { return p[i]; }
-};
+struct XL<PERF_F32> : VecF4 {};
 template <>
-struct XL<PERF_BF16> {
-    const ushort4* __restrict__ p;
-    __device__ __forceinline__ float4 operator()(int i) const {
-        ushort4 q = p[i];
-        return make_float4(bf16_to_f32(q.x), bf16_to_f32(q.y), bf16_to_f32(q.z), bf16_to_f32(q.w));
+struct XL<PERF_BF16> {  // bfloat16 x 4 per unit
+    __amdgpu_buffer_rsrc_t r;
+    static constexpr int kBytes = 8;
+    __device__ __forceinline__ float4 load(int voff, int soff) const {
+        const auto q = __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0);
+        const unsigned a = (unsigned)q[0], b = (unsigned)q[1];
+        return make_float4(__uint_as_float(a << 16), __uint_as_float(a & 0xffff0000u), __uint_as_float(b << 16),
+                           __uint_as_float(b & 0xffff0000u));
     }
+    __device__ __forceinline__ float4 operator()(int i) const { return load(i * kBytes, 0); }
 };
 
 struct Ray {
@@ -824,19 +841,43 @@ struct Depth {
     __device__ __forceinline__ float value() const { return s - c; }
 };
 
+// Byte offsets of the 8 trilinear corners from the lower corner (wave-uniform).
+struct CornerOffs {
+    int o[8];
+};
+template <int BYTES>
+__device__ __forceinline__ CornerOffs corner_offs(int nx, int nxy) {
+    CornerOffs k;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) k.o[j] = corner_off(j, nx, nxy) * BYTES;
+    return k;
+}
+
+// Gather the trilinear sample of a float4-per-unit vector at corners c.
+template <class L>
+__device__ __forceinline__ float4 gather4(const L& X, const Corners& c, const CornerOffs& k) {
+    const int base = c.v * L::kBytes;
+    float4 s = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const float4 q = X.load(base, k.o[j]);
+        s.x += c.w[j] * q.x;
+        s.y += c.w[j] * q.y;
+        s.z += c.w[j] * q.z;
+        s.w += c.w[j] * q.w;
+    }
+    return s;
+}
+
 // Gather the trilinear sample of (c, sigma) at corners c.
 template <int PD>
 __device__ __forceinline__ void gather(XL<PD> X, const Corners& c, int nx, int nxy, float& sg, float& c0, float& c1,
                                        float& c2) {
-    sg = c0 = c1 = c2 = 0.0f;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-        const float4 q = X(c.v + corner_off(j, nx, nxy));
-        c0 += c.w[j] * q.x;
-        c1 += c.w[j] * q.y;
-        c2 += c.w[j] * q.z;
-        sg += c.w[j] * q.w;
-    }
+    const float4 s = gather4(X, c, corner_offs<XL<PD>::kBytes>(nx, nxy));
+    c0 = s.x;
+    c1 = s.y;
+    c2 = s.z;
+    sg = s.w;
 }
 
 // The march of a wave is aligned in depth: lane i starts its first sample at wave step
@@ -844,7 +885,7 @@ __device__ __forceinline__ void gather(XL<PD> X, const Corners& c, int nx, int n
 // about the same distance from the camera (the rays of an 8x8 tile are nearly parallel).
 // Every lane still takes its own samples in its own order; only their timing changes.
 template <int PD, bool TAN>
-__device__ __forceinline__ void forward(const Geo& G, const Ray& r, bool live, XL<PD> X, const float4* __restrict__ V,
+__device__ __forceinline__ void forward(const Geo& G, const Ray& r, bool live, XL<PD> X, VecF4 V,
                                         float H[3], float& Texit, float& Tdexit, float Hd[3], Depth& depth,
                                         float thresh = 0.0f) {
     float T = 1.0f, Td = 0.0f;
@@ -868,14 +909,11 @@ __device__ __forceinline__ void forward(const Geo& G, const Ray& r, bool live, X
         gather<PD>(X, c, nx, nxy, sg, c0, c1, c2);
         float sgd = 0.0f, cd0 = 0.0f, cd1 = 0.0f, cd2 = 0.0f;
         if constexpr (TAN) {
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const float4 t = V[c.v + corner_off(i, nx, nxy)];
-                cd0 += c.w[i] * t.x;
-                cd1 += c.w[i] * t.y;
-                cd2 += c.w[i] * t.z;
-                sgd += c.w[i] * t.w;
-            }
+            const float4 t = gather4(V, c, corner_offs<VecF4::kBytes>(nx, nxy));
+            cd0 = t.x;
+            cd1 = t.y;
+            cd2 = t.z;
+            sgd = t.w;
         }
         const float tau = sg * dk;
         depth.add(tau);
@@ -917,7 +955,7 @@ __device__ __forceinline__ void forward(const Geo& G, const Ray& r, bool live, X
             c2 += tx.w[j] * q.z;
             al += tx.w[j] * q.w;
             if constexpr (TAN) {
-                const float4 t = V[tx.t[j]];
+                const float4 t = V(tx.t[j]);
                 cd0 += tx.w[j] * t.x;
                 cd1 += tx.w[j] * t.y;
                 cd2 += tx.w[j] * t.z;
@@ -1438,8 +1476,9 @@ __global__ __launch_bounds__(kBlock) void k_ray(Geo G, RayArgs A) {
     if (A.done && *A.done) return;
     const Pix p = pixel_of(G);
     const int wave = threadIdx.x >> 6;
+    const int units = G.nvox + G.n_layers * G.env_w * G.env_h;
     XL<PD> X;
-    X.p = reinterpret_cast<decltype(X.p)>(A.x);
+    X.r = make_rsrc(A.x, (unsigned)units * XL<PD>::kBytes);
     Ray r;
     make_ray(G, A.cams[p.cam], p.px, p.py, p.ray, r);
     if (!p.active) {
@@ -1449,9 +1488,11 @@ __global__ __launch_bounds__(kBlock) void k_ray(Geo G, RayArgs A) {
     float H[3], Hd[3], Texit, Tdexit;
     Depth depth;
     if constexpr (MODE == M_JVP || MODE == M_JTJ) {
-        forward<PD, true>(G, r, p.active, X, reinterpret_cast<const float4*>(A.v), H, Texit, Tdexit, Hd, depth);
+        VecF4 V;
+        V.r = make_rsrc(A.v, (unsigned)units * VecF4::kBytes);
+        forward<PD, true>(G, r, p.active, X, V, H, Texit, Tdexit, Hd, depth);
     } else {
-        forward<PD, false>(G, r, p.active, X, nullptr, H, Texit, Tdexit, Hd, depth,
+        forward<PD, false>(G, r, p.active, X, VecF4{}, H, Texit, Tdexit, Hd, depth,
                            MODE == M_RENDER ? A.thresh : 0.0f);
     }
     // auxiliary opacity residual (Sec. III-I, Eq. 10): r4 = lambda (1 - 4 (T - 1/2)^2) =

@@ -145,7 +145,7 @@ __global__ void k_invert(int kind, const float* __restrict__ blocks, int64_t uni
         } else {
             float4* o = reinterpret_cast<float4*>(out) + 2 * u;
             const double m = fmax(d, f);
-            if (!(m > 0.0)) {
+            if (!(m > 0.0) || !isfinite(d + e0 + e1 + e2 + f)) {  // no ray, or a non-finite block
                 o[0] = o[1] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
                 continue;
             }
@@ -358,9 +358,11 @@ __global__ void k_features(const void* __restrict__ xp, int x_bf16, const float*
         }
         const float* s = sums + 6 * u;
         const float* b = blocks + 5 * u;
+        // the means divide sums that can be far below the FP32 normal range (units seen only
+        // through near-opaque matter): in double
         const float w = s[0];
-        const float iw = w > 0.0f ? 1.0f / w : 0.0f;
-        const float iwt = s[1] > 0.0f ? 1.0f / s[1] : 0.0f;
+        const double iw = w > 0.0f ? 1.0 / (double)w : 0.0;
+        const double iwt = s[1] > 0.0f ? 1.0 / (double)s[1] : 0.0;
         float* f = feat + 12 * u;
         f[0] = xv.w;
         f[1] = xv.x;
@@ -369,11 +371,11 @@ __global__ void k_features(const void* __restrict__ xp, int x_bf16, const float*
         f[4] = logf(fmaxf(b[0], 0.0f) + 1e-12f);
         f[5] = logf(fmaxf(b[4], 0.0f) + 1e-12f);
         f[6] = log1pf(w);
-        f[7] = s[1] * iw;
-        f[8] = s[2] * iwt;  // colour behind, unattenuated: sum w G / sum w T
-        f[9] = s[3] * iwt;
-        f[10] = s[4] * iwt;
-        f[11] = s[5] * iw;
+        f[7] = (float)(s[1] * iw);
+        f[8] = (float)(s[2] * iwt);  // colour behind, unattenuated: sum w G / sum w T
+        f[9] = (float)(s[3] * iwt);
+        f[10] = (float)(s[4] * iwt);
+        f[11] = (float)(s[5] * iw);
     }
 }
 
@@ -390,9 +392,17 @@ __device__ __forceinline__ unsigned mix32(unsigned h) {
     h ^= h >> 16;
     return h;
 }
-__device__ __forceinline__ bool keep_row(const float* __restrict__ blocks, int64_t u, unsigned seed, unsigned thresh) {
+// A row is eligible when some ray touches the unit and its block and features are finite (a unit
+// whose parameters ran off during a poorly conditioned step can carry infinite sums).
+__device__ __forceinline__ bool keep_row(const float* __restrict__ feat, const float* __restrict__ blocks, int64_t u,
+                                         unsigned seed, unsigned thresh) {
     const float* b = blocks + 5 * u;
-    return fmaxf(b[0], b[4]) > 0.0f && mix32(seed ^ mix32((unsigned)u ^ (unsigned)(u >> 32) * 0x9e3779b9u)) < thresh;
+    bool ok = fmaxf(b[0], b[4]) > 0.0f;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) ok &= isfinite(b[i]);
+#pragma unroll
+    for (int i = 0; i < 12; ++i) ok &= isfinite(feat[12 * u + i]);
+    return ok && mix32(seed ^ mix32((unsigned)u ^ (unsigned)(u >> 32) * 0x9e3779b9u)) < thresh;
 }
 
 // kept rows of the workgroup's chunk before each thread's unit in this pass of the chunk
@@ -414,7 +424,8 @@ __device__ __forceinline__ int block_exclusive_count(bool flag, int* total) {
     return before;
 }
 
-__global__ __launch_bounds__(kVecBlock) void k_rows_count(const float* __restrict__ blocks, int64_t units,
+__global__ __launch_bounds__(kVecBlock) void k_rows_count(const float* __restrict__ feat,
+                                                          const float* __restrict__ blocks, int64_t units,
                                                           int64_t chunk, unsigned seed, unsigned thresh,
                                                           long long* counts) {
     const int64_t lo = blockIdx.x * chunk, hi = min(lo + chunk, units);
@@ -422,7 +433,7 @@ __global__ __launch_bounds__(kVecBlock) void k_rows_count(const float* __restric
     for (int64_t base = lo; base < hi; base += kVecBlock) {
         const int64_t u = base + threadIdx.x;
         int total;
-        (void)block_exclusive_count(u < hi && keep_row(blocks, u, seed, thresh), &total);
+        (void)block_exclusive_count(u < hi && keep_row(feat, blocks, u, seed, thresh), &total);
         c += total;
     }
     if (threadIdx.x == 0) counts[blockIdx.x] = c;
@@ -448,7 +459,7 @@ __global__ __launch_bounds__(kVecBlock) void k_rows_write(const float* __restric
     long long at = offsets[blockIdx.x];
     for (int64_t base = lo; base < hi; base += kVecBlock) {
         const int64_t u = base + threadIdx.x;
-        const bool k = u < hi && keep_row(blocks, u, seed, thresh);
+        const bool k = u < hi && keep_row(feat, blocks, u, seed, thresh);
         int total;
         const int before = block_exclusive_count(k, &total);
         const long long dst = at + before;
@@ -596,7 +607,8 @@ hipError_t launch_training_rows(const float* feat, const float* blocks, int64_t 
     const int64_t chunk = (units + nb - 1) / nb;
     const double t = fmin(fmax((double)keep, 0.0), 1.0) * 4294967296.0;
     const unsigned thresh = t >= 4294967295.0 ? 0xffffffffu : (unsigned)t;
-    hipLaunchKernelGGL(k_rows_count, dim3(nb), dim3(kVecBlock), 0, st, blocks, units, chunk, seed, thresh, counts);
+    hipLaunchKernelGGL(k_rows_count, dim3(nb), dim3(kVecBlock), 0, st, feat, blocks, units, chunk, seed, thresh,
+                       counts);
     hipLaunchKernelGGL(k_rows_offsets, dim3(1), dim3(64), 0, st, counts, nb);
     hipLaunchKernelGGL(k_rows_write, dim3(nb), dim3(kVecBlock), 0, st, feat, blocks, units, chunk, seed, thresh, counts,
                        cap, feat_out, blocks_out);

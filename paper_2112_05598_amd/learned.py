@@ -79,7 +79,7 @@ def generate(workloads, gn_steps=5, per_step=65536, pcg_iters=5, seed=0, log=pri
 def _sample(sc: Scene, f, b, key: int, per_step: int):
     """About per_step rows of the touched units, drawn by the library (count first, then keep
     each with probability per_step / touched)."""
-    _, _, touched = sc.training_rows(f, b, key, 1.0, 0)
+    _, _, touched = sc.training_rows(f, b, key, 1.0, 0)  # eligible rows: touched, finite
     keep = min(1.0, per_step / max(touched, 1))
     fo, bo, _ = sc.training_rows(f, b, key, keep, int(per_step * 1.2) + 1024)
     return fo, bo
@@ -116,7 +116,10 @@ def train(feat, blocks, epochs=4, batch=16384, lr=5e-4, seed=0, damp=0.0, log=pr
             fb = feat[idx].contiguous()
             bb = blocks[idx].contiguous()
             mlp_train_step(w32, wbf, m, v, t, lr, norm, fb, bb, loss, grad, damp=damp)
-            tot += loss.item()
+            lv = loss.item()
+            if not np.isfinite(lv):
+                raise FloatingPointError(f"non-finite training loss at step {t}")
+            tot += lv
             cnt += 1
         hist.append(tot / max(cnt, 1))
         log(f"[learned] damp {damp} epoch {ep}: mean loss {hist[-1]:.5f}")
