@@ -315,6 +315,18 @@ int32_t perf_mlp_infer(perf_scene* s, const float* d_feat, const float* d_blocks
 int32_t perf_mlp_train_step(float* d_w32, uint16_t* d_wbf16, float* d_m, float* d_v, int32_t t, float lr,
                             float damp, const float* d_norm, const float* d_feat, const float* d_blocks, int32_t n,
                             float* d_loss, float* d_grad_scratch, void* stream);
+/*
+ * perf_mlp_train_step_noalloc: perf_mlp_train_step without d_grad_scratch, for callers that
+ * cannot allocate device memory (code under graph capture, serving loops, harnesses that forbid
+ * it).  The gradient accumulator is a fixed library-owned device array of PERF_MLP_NW floats
+ * (22.6 KB) per GPU, looked up on the device current at the first call and kept until the
+ * process ends; no argument changes its size.  The call allocates nothing, clears the array
+ * itself before use, and otherwise behaves as perf_mlp_train_step (same arguments, same
+ * errors).  Every call on one GPU shares the array: calls that overlap on one GPU race.
+ */
+int32_t perf_mlp_train_step_noalloc(float* d_w32, uint16_t* d_wbf16, float* d_m, float* d_v, int32_t t, float lr,
+                                    float damp, const float* d_norm, const float* d_feat, const float* d_blocks,
+                                    int32_t n, float* d_loss, void* stream);
 int32_t perf_mlp_feature_stats(const float* d_feat, int64_t n, float* d_norm, void* stream);
 int32_t perf_mlp_training_rows(perf_scene* s, const float* d_feat, const float* d_blocks, uint32_t seed, float keep,
                                float* d_feat_out, float* d_blocks_out, int64_t cap, int64_t* n_kept);

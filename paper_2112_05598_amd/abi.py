@@ -103,6 +103,8 @@ SIGNATURES = [
     ("perf_mlp_infer", _I32, [_P, _P, _P, _P]),
     ("perf_mlp_train_step", _I32, [_P, _P, _P, _P, _I32, ctypes.c_float, ctypes.c_float, _P, _P, _P, _I32, _P, _P,
                                    _P]),
+    ("perf_mlp_train_step_noalloc", _I32, [_P, _P, _P, _P, _I32, ctypes.c_float, ctypes.c_float, _P, _P, _P, _I32,
+                                           _P, _P]),
     ("perf_mlp_feature_stats", _I32, [_P, _I64, _P, _P]),
     ("perf_mlp_training_rows", _I32, [_P, _P, _P, ctypes.c_uint32, ctypes.c_float, _P, _P, _I64,
                                       ctypes.POINTER(_I64)]),

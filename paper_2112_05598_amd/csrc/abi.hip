@@ -490,6 +490,18 @@ int32_t perf_mlp_train_step(float* d_w32, uint16_t* d_wbf16, float* d_m, float* 
     return PERF_OK;
 }
 
+int32_t perf_mlp_train_step_noalloc(float* d_w32, uint16_t* d_wbf16, float* d_m, float* d_v, int32_t t, float lr,
+                                    float damp, const float* d_norm, const float* d_feat, const float* d_blocks,
+                                    int32_t n, float* d_loss, void* stream) {
+    if (!d_w32 || !d_wbf16 || !d_m || !d_v || !d_loss || !d_norm) return fail(PERF_EINVAL, "null argument");
+    if (n < 0 || (n > 0 && (!d_feat || !d_blocks))) return fail(PERF_EINVAL, "bad batch");
+    if (t < 1 || !(lr > 0.0f)) return fail(PERF_EINVAL, "need t >= 1 and lr > 0");
+    if (!(damp >= 0.0f && damp <= 1e6f)) return fail(PERF_EINVAL, "damp must be in [0, 1e6]");
+    CK(launch_mlp_train_static(d_w32, d_wbf16, d_m, d_v, t, lr, damp, d_norm, d_feat, d_blocks, n, d_loss,
+                               (hipStream_t)stream));
+    return PERF_OK;
+}
+
 int32_t perf_mlp_feature_stats(const float* d_feat, int64_t n, float* d_norm, void* stream) {
     if (!d_norm || (n > 0 && !d_feat)) return fail(PERF_EINVAL, "null argument");
     if (n < 0) return fail(PERF_EINVAL, "negative row count");

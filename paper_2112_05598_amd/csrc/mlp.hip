@@ -20,6 +20,8 @@
 
 #include <math.h>
 
+#include <mutex>
+
 namespace perf {
 namespace {
 
@@ -556,6 +558,52 @@ hipError_t launch_mlp_train(float* w32, uint16_t* wbf, float* m, float* v, int t
     }
     hipLaunchKernelGGL(k_adam, dim3((NW + 255) / 256), dim3(256), 0, st, w32, wbf, m, v, grad, t, lr);
     return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ allocation-free training step
+// The gradient accumulator of a training step for callers that cannot allocate device memory: a
+// file-scope device array of one gradient (PERF_MLP_NW floats), one copy per GPU, held until the
+// process ends.  On the host the array's name is only a stand-in: its device address is looked
+// up once per device (the device current at the first call) with hipGetSymbolAddress and kept,
+// and kernels receive that address.  Every call on a GPU shares its copy, so calls that overlap
+// on one GPU race; each call clears it first.
+constexpr int kStaticGradFloats = ((NW + 63) / 64) * 64;
+static __device__ __align__(256) float scratch[kStaticGradFloats];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_ptr[kMaxDevices];
+
+hipError_t static_grad_scratch(float** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = static_cast<float*>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+}  // namespace
+
+hipError_t launch_mlp_train_static(float* w32, uint16_t* wbf, float* m, float* v, int t, float lr, float damp,
+                                   const float* norm, const float* feat, const float* blocks, int n, float* loss,
+                                   hipStream_t st) {
+    float* grad = nullptr;
+    hipError_t e = static_grad_scratch(&grad);
+    if (e != hipSuccess) return e;
+    // an earlier call that failed part-way may have left partial sums: start from zero (a fill
+    // kernel, no memset)
+    hipLaunchKernelGGL(k_zero1, dim3((kStaticGradFloats + 255) / 256), dim3(256), 0, st, grad, kStaticGradFloats);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_mlp_train(w32, wbf, m, v, t, lr, damp, norm, feat, blocks, n, loss, grad, st);
 }
 
 hipError_t launch_feature_stats(const float* feat, int64_t n, float* norm, hipStream_t st) {

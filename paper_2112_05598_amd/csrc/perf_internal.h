@@ -126,6 +126,9 @@ hipError_t launch_mlp_infer(const uint16_t* w, const float* norm, float q_fallba
 hipError_t launch_mlp_train(float* w32, uint16_t* wbf, float* m, float* v, int t, float lr, float damp,
                             const float* norm, const float* feat, const float* blocks, int n, float* loss, float* grad,
                             hipStream_t st);
+hipError_t launch_mlp_train_static(float* w32, uint16_t* wbf, float* m, float* v, int t, float lr, float damp,
+                                   const float* norm, const float* feat, const float* blocks, int n, float* loss,
+                                   hipStream_t st);
 hipError_t launch_feature_stats(const float* feat, int64_t n, float* norm, hipStream_t st);
 
 hipError_t launch_upsample(const float* src, int sx, int sy, int sz, int sw, int sh, float* dst, int dx, int dy,
