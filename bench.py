@@ -180,10 +180,13 @@ def main():
                "pcg_iters": [s["pcg_iters"] for s in stats], "gamma": [s["gamma"] for s in stats]},
         "footprint": {"sum_U": int(tot[0]), "layer_hits": int(tot[1]), "rays_in_grid": int(tot[2])},
     }
-    if not args.no_learned and args.precond == "jacobi":
+    from paper_2112_05598_amd import learned as lrn
+    if not args.no_learned and args.precond == "jacobi" and not os.path.exists(lrn.WEIGHTS):
+        print(f"[bench] no learned weights at {lrn.WEIGHTS}: learned comparison skipped", file=sys.stderr, flush=True)
+        out["gn_learned_vs_jacobi"] = None
+    elif not args.no_learned and args.precond == "jacobi":
         # GN time-to-residual: the learned preconditioner, from the same start, until it reaches
         # the objective the timed Jacobi steps ended at (same PCG iterations per step)
-        from paper_2112_05598_amd import learned as lrn
         lrn.load_model(device="cuda:0").install(sc)
         F_target = stats[-1]["F_after"]
         run = lrn.gn_run(sc, x0, "learned", args.steps + 3, args.pcg, F_stop=F_target)

@@ -79,7 +79,10 @@ enum {
     PERF_FLAG_STALL = 2,       /* R / R_prev above stall_ratio (the early exit of Alg. 2) */
     PERF_FLAG_CONVERGED = 4,   /* R < abs_eps or sqrt(R/R0) <= rel_tol */
     PERF_FLAG_LS_CAPPED = 8,   /* line search hit ls_max trials */
-    PERF_FLAG_NO_DESCENT = 16  /* no trial lowered F: gamma = 0, x unchanged */
+    PERF_FLAG_NO_DESCENT = 16, /* no trial lowered F: gamma = 0, x unchanged */
+    PERF_FLAG_FALLBACK = 32    /* the learned solve broke down, stalled or found no descent; the
+                                  step was solved again with PERF_PRECOND_BLOCK4 (the other flags,
+                                  the history and pcg_iters describe that second solve) */
 };
 
 typedef struct {
@@ -123,14 +126,17 @@ typedef struct {
 
 typedef struct {
     double F_before, F_after, gamma;
-    int32_t pcg_iters, ls_trials, flags, reserved;
+    int32_t pcg_iters, ls_trials, flags;
+    int32_t fallback_iters;      /* PCG iterations of a discarded learned solve (0: none) */
     double R0;
     double R[PERF_MAX_PCG];      /* r_{k+1}^T r_{k+1} after update k */
     double alpha[PERF_MAX_PCG];  /* alpha_k */
     double beta[PERF_MAX_PCG];   /* beta_k (one fewer than alpha) */
     double pAp[PERF_MAX_PCG];    /* p_k^T A p_k */
     float ms_phase[8];           /* grad+precond, invert, pcg, line search, update, total,
-                                    J^T J v kernel time summed over the solve, number of those launches */
+                                    J^T J v kernel time summed over the solve, number of those launches
+                                    (with a fallback: the final solve's; the discarded solve, its line
+                                    search and the block inversion count in the pcg phase) */
 } perf_gn_stats;
 
 typedef struct perf_scene perf_scene;
@@ -209,6 +215,9 @@ int32_t perf_build_precond(perf_scene* s, const void* d_x, int32_t kind, float* 
  * d_x    device FP32 master parameters [P], updated in place (with PERF_BF16 the library keeps
  *        the bfloat16 copy used for every gather in its workspace).
  * stats  host output, may be NULL.
+ * With PERF_PRECOND_LEARNED, a solve that ends in breakdown, a stall or a line search without
+ * descent is discarded and the step is solved again, from Delta_0 = 0, with the exact block
+ * inverse (PERF_FLAG_FALLBACK).
  * Errors: PERF_EINVAL (bad options, no targets), PERF_ENUMERIC (checks = 1 and non-finite x or
  * targets).  PCG breakdown and an unproductive line search are reported in stats->flags.
  */

@@ -5,6 +5,8 @@
   summarise:  python -m measure.profile_kernels summarise --fetch F.db --write W.db --out traffic.json \
                   [--atomic A.db --timing-json T.json]
   counters:   python -m measure.profile_kernels counters --db P1.db [--db P2.db ...] --out counters.json
+  report:     python -m measure.profile_kernels report --counters counters.json --traffic traffic.json \
+                  --stats kernel_stats.csv [--out table.md]
 
 `run` launches, on the named workload at the initial parameters: the J^T J v product `--launches`
 times (seeded random v), the gradient + exact-block pass, the feature pass of the learned
@@ -18,8 +20,11 @@ Run it under `rocprofv3 --pmc <counters>` once per counter set.
 J^T J v kernel, scales it by (known copy bytes / counted copy bytes) of the calibration copy, and
 writes the HBM bytes per dispatch together with the sha256 of the kernel source they were
 measured on; with --atomic (a TCC_ATOMIC pass) and --timing-json it adds the L2 atomic requests
-per second of the J^T J v kernel against those of the probe.  `counters` averages every counter of
-the given databases per dispatch of each kernel.
+per second of the J^T J v kernel against those of the probe, and the HBM bytes per dispatch of the
+other profiled kernels.  `counters` averages every counter of the given databases per dispatch of
+each kernel.  `report` writes the tables of the kernel summary: durations from the kernel trace,
+VALU issue share (wave instructions over one per CU per cycle at 2.4 GHz, the wave64 FP32 rate
+without packed math), the share of wave cycles spent waiting on LDS, MFMA flop/s and HBM bytes.
 """
 from __future__ import annotations
 
@@ -166,6 +171,15 @@ def summarise(args):
         total += b
         out["kernel"] = jname
     out["bytes_per_dispatch"] = total
+    # the other profiled kernels' HBM bytes, scaled by the same calibration copy
+    out["kernels"] = {}
+    for counter, db in (("FETCH_SIZE", args.fetch), ("WRITE_SIZE", args.write)):
+        per = _per_dispatch(db, counter)
+        scale = out[counter]["scale"]
+        for kname, (kib, n) in per.items():
+            short = next((v for k, v in KERNELS.items() if k in kname), None)
+            if short is not None:
+                out["kernels"].setdefault(short, {"kernel": kname})[counter] = kib * 1024.0 * scale
     if args.atomic and args.timing_json:
         tm = json.load(open(args.timing_json))
         per = _per_dispatch(args.atomic, "TCC_ATOMIC")
@@ -220,6 +234,69 @@ def counters(args):
     print(json.dumps(out, indent=1))
 
 
+# peaks used by the report (MI355X): HBM bytes/s, dense bf16 MFMA flop/s, compute units, clock
+HBM_PEAK = 8.0e12
+BF16_PEAK = 2.5e15
+N_CU, CLOCK_HZ = 256, 2.4e9
+MFMA_FLOPS = 32 * 32 * 8 * 2  # one v_mfma_f32_32x32x8_bf16 wave instruction
+
+
+def _trace_ms(csv_path: str):
+    """{short kernel name: (calls, average ms)} from a rocprofv3 --stats kernel_stats.csv."""
+    import csv
+    out = {}
+    with open(csv_path) as f:
+        for row in csv.DictReader(f):
+            short = next((v for k, v in KERNELS.items() if k in row["Name"]), None)
+            if short is not None:
+                out[short] = (int(row["Calls"]), float(row["AverageNs"]) * 1e-6)
+    return out
+
+
+def report(args):
+    """Markdown tables of the kernel trace, the SQ counters and the HBM counters per kernel."""
+    cnt = json.load(open(args.counters))
+    trf = json.load(open(args.traffic))
+    tr = _trace_ms(args.stats)
+    if cnt["kernel_sha"] != trf["kernel_sha"]:
+        raise SystemExit("counter and traffic summaries come from different kernel sources")
+    lines = [f"Kernel source sha256[:16] = `{cnt['kernel_sha']}`, workload {cnt['workload']}.", "",
+             "| kernel | calls | avg ms (trace) | VALU wave-instr | VALU issue share | LDS instr | "
+             "LDS-wait share | VMEM rd instr | MFMA instr | HBM GB (counted) | HBM GB/s | % HBM peak |",
+             "|---|---|---|---|---|---|---|---|---|---|---|---|"]
+    for short in ("jtj", "grad", "feat", "mlp_infer", "mlp_train"):
+        k = cnt["kernels"].get(short)
+        if k is None or short not in tr:
+            continue
+        calls, ms = tr[short]
+        v = lambda c: k[c]["per_dispatch"]
+        valu_share = v("SQ_INSTS_VALU") / (N_CU * CLOCK_HZ * ms * 1e-3)
+        lds_wait = v("SQ_WAIT_INST_LDS") / v("SQ_WAVE_CYCLES")
+        hb = trf.get("kernels", {}).get(short, {})
+        gb = (hb.get("FETCH_SIZE", 0.0) + hb.get("WRITE_SIZE", 0.0)) / 1e9
+        gbs = gb / (ms * 1e-3)
+        lines.append(f"| {short} | {calls} | {ms:.3f} | {v('SQ_INSTS_VALU'):.4g} | {valu_share:.3f} | "
+                     f"{v('SQ_INSTS_LDS'):.4g} | {lds_wait:.3f} | {v('SQ_INSTS_VMEM_RD'):.4g} | "
+                     f"{v('SQ_INSTS_MFMA'):.4g} | {gb:.3f} | {gbs:.1f} | {100 * gbs * 1e9 / HBM_PEAK:.1f} |")
+    lines += ["", "MFMA kernels (bf16 32x32x8 MFMA, 16384 flop per wave instruction):", "",
+              "| kernel | MFMA flop per dispatch | TFLOP/s | % of 2.5 PFLOP/s | MFMA busy / SQ busy cycles |",
+              "|---|---|---|---|---|"]
+    for short in ("mlp_infer", "mlp_train"):
+        k = cnt["kernels"].get(short)
+        if k is None or short not in tr:
+            continue
+        ms = tr[short][1]
+        fl = k["SQ_INSTS_MFMA"]["per_dispatch"] * MFMA_FLOPS
+        busy = k["SQ_VALU_MFMA_BUSY_CYCLES"]["per_dispatch"] / max(k["SQ_BUSY_CYCLES"]["per_dispatch"], 1.0)
+        lines.append(f"| {short} | {fl:.4g} | {fl / (ms * 1e-3) / 1e12:.2f} | "
+                     f"{100 * fl / (ms * 1e-3) / BF16_PEAK:.2f} | {busy:.2f} |")
+    text = "\n".join(lines) + "\n"
+    if args.out:
+        with open(args.out, "w") as f:
+            f.write(text)
+    print(text)
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -240,8 +317,13 @@ def main():
     c.add_argument("--db", action="append", required=True)
     c.add_argument("--workload", default="cfg2")
     c.add_argument("--out", required=True)
+    q = sub.add_parser("report")
+    q.add_argument("--counters", required=True)
+    q.add_argument("--traffic", required=True)
+    q.add_argument("--stats", required=True, help="rocprofv3 --stats kernel_stats.csv")
+    q.add_argument("--out", default="")
     args = ap.parse_args()
-    {"run": run, "summarise": summarise, "counters": counters}[args.cmd](args)
+    {"run": run, "summarise": summarise, "counters": counters, "report": report}[args.cmd](args)
 
 
 if __name__ == "__main__":

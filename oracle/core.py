@@ -520,7 +520,11 @@ def upsample(spec_from, x_from: np.ndarray, spec_to) -> np.ndarray:
 def gn_step(scene: OracleScene, x: np.ndarray, targets: np.ndarray, precond: str = "jacobi", max_iters: int = 20,
             rel_tol: float = 0.0, abs_eps: float = 0.0, stall_ratio: float = 0.0, line_search_on: bool = True,
             ls_factor: float = 0.7, ls_max: int = 20, learned_minv=None):
-    """One Gauss-Newton step (Eq. 7): b = -J^T r, PCG on J^T J Delta = b, Alg. 3, projected update."""
+    """One Gauss-Newton step (Eq. 7): b = -J^T r, PCG on J^T J Delta = b, Alg. 3, projected update.
+
+    With precond='learned' (learned_minv: the predicted inverses), a solve that breaks down,
+    stalls or whose line search finds no descent is discarded and the step solved again with
+    the exact block inverse; fallback_iters then holds the discarded solve's iterations."""
     x = np.asarray(x, dtype=np.float64)
     grad, blocks, F0 = scene.grad_blocks(x, targets)
     if precond == "jacobi":
@@ -531,18 +535,26 @@ def gn_step(scene: OracleScene, x: np.ndarray, targets: np.ndarray, precond: str
         data = learned_minv
     else:
         data = None
-    res = pcg(lambda p: scene.apply_JtJ(x, p), grad, lambda r: apply_precond(precond, data, r),
-              max_iters=max_iters, rel_tol=rel_tol, abs_eps=abs_eps, stall_ratio=stall_ratio)
-    delta = res.x
     spec = scene.spec
 
-    def objective(g):
-        return scene.render(project(spec, x + g * delta), targets)[2]
+    def solve(kind, minv):
+        res = pcg(lambda p: scene.apply_JtJ(x, p), grad, lambda r: apply_precond(kind, minv, r),
+                  max_iters=max_iters, rel_tol=rel_tol, abs_eps=abs_eps, stall_ratio=stall_ratio)
 
-    if line_search_on:
-        gamma, mu, n_ls, capped = line_search(objective, F0, ls_factor, ls_max)
-    else:
-        gamma, mu, n_ls, capped = 1.0, objective(1.0), 1, False
+        def objective(g):
+            return scene.render(project(spec, x + g * res.x), targets)[2]
+
+        if line_search_on:
+            return (res,) + tuple(line_search(objective, F0, ls_factor, ls_max))
+        return res, 1.0, objective(1.0), 1, False
+
+    res, gamma, mu, n_ls, capped = solve(precond, data)
+    fallback_iters = None
+    if precond == "learned" and (res.flags & {"breakdown", "stall"} or gamma == 0.0):
+        # a failed learned solve is replaced by the exact block-Jacobi solve (reading of this library)
+        fallback_iters = res.iters
+        res, gamma, mu, n_ls, capped = solve("block", block_inverse(blocks))
+    delta = res.x
     x_new = project(spec, x + gamma * delta)
     return dict(x=x_new, delta=delta, gamma=gamma, F_before=F0, F_after=mu, pcg=res, blocks=blocks, grad=grad,
-                n_ls=n_ls, ls_capped=capped)
+                n_ls=n_ls, ls_capped=capped, fallback_iters=fallback_iters)

@@ -20,6 +20,7 @@ PERF_OK, PERF_EINVAL, PERF_ENOMEM, PERF_EDEVICE, PERF_ENUMERIC, PERF_EUNSUPPORTE
 PERF_F32, PERF_BF16 = 0, 1
 PERF_PRECOND_NONE, PERF_PRECOND_JACOBI, PERF_PRECOND_BLOCK4, PERF_PRECOND_LEARNED = 0, 1, 2, 3
 PERF_FLAG_BREAKDOWN, PERF_FLAG_STALL, PERF_FLAG_CONVERGED, PERF_FLAG_LS_CAPPED, PERF_FLAG_NO_DESCENT = 1, 2, 4, 8, 16
+PERF_FLAG_FALLBACK = 32
 
 
 class perf_scene_desc(ctypes.Structure):
@@ -64,7 +65,7 @@ class perf_gn_stats(ctypes.Structure):
     _fields_ = [
         ("F_before", ctypes.c_double), ("F_after", ctypes.c_double), ("gamma", ctypes.c_double),
         ("pcg_iters", ctypes.c_int32), ("ls_trials", ctypes.c_int32), ("flags", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("fallback_iters", ctypes.c_int32),
         ("R0", ctypes.c_double),
         ("R", ctypes.c_double * PERF_MAX_PCG),
         ("alpha", ctypes.c_double * PERF_MAX_PCG),

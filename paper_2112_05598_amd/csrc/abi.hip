@@ -531,60 +531,17 @@ static int32_t learned_minv(perf_scene* s, const void* xg, const float* x32) {
     return PERF_OK;
 }
 
-int32_t perf_gn_step(perf_scene* s, float* d_x, const perf_pcg_opts* opts, perf_gn_stats* stats) {
-    if (!s || !d_x || !opts) return fail(PERF_EINVAL, "null argument");
-    if (!s->targets) return fail(PERF_EINVAL, "scene has no targets");
-    if (opts->max_iters < 1 || opts->max_iters > PERF_MAX_PCG) return fail(PERF_EINVAL, "max_iters must be 1..256");
-    if (opts->precond < PERF_PRECOND_NONE || opts->precond > PERF_PRECOND_LEARNED)
-        return fail(PERF_EINVAL, "bad preconditioner kind");
-    if (opts->line_search && (!(opts->ls_factor > 0.0f && opts->ls_factor < 1.0f) || opts->ls_max < 1))
-        return fail(PERF_EINVAL, "line search needs 0 < ls_factor < 1 and ls_max >= 1");
-    if (opts->precond == PERF_PRECOND_LEARNED && !s->mlp_ready)
-        return fail(PERF_EINVAL, "learned preconditioner has no weights (perf_mlp_set_weights)");
+// PCG (Alg. 2) from Delta_0 = 0 on the gradient in s->vr, then the line search (Alg. 3).
+// Records ev[0] after the solve and ev[1] after the search; the J^T J v launches are bracketed
+// by jev[2k], jev[2k+1].
+struct SolveOut {
+    int flags = 0, iters = 0, trials = 0, n_jtj = 0;
+    double F0 = 0.0, gamma = 0.0, mu_acc = 0.0;
+};
+
+static int32_t solve_and_search(perf_scene* s, const void* xg, float* d_x, const perf_pcg_opts* opts,
+                                int apply_kind, hipEvent_t* ev, hipEvent_t* jev, SolveOut* out) {
     hipStream_t st = s->stream;
-    // phase events, plus a pair around every J^T J v launch (its kernel time, for the roofline)
-    constexpr int kPh = 6;
-    hipEvent_t ev[kPh + 2 * PERF_MAX_PCG];
-    const int n_ev = kPh + 2 * opts->max_iters;
-    for (int i = 0; i < n_ev; ++i) CK(hipEventCreate(&ev[i]));
-    struct EvGuard {
-        hipEvent_t* e;
-        int n;
-        ~EvGuard() {
-            for (int i = 0; i < n; ++i) (void)hipEventDestroy(e[i]);
-        }
-    } guard{ev, n_ev};
-    int n_jtj = 0;
-    CK(hipEventRecord(ev[0], st));
-    if (s->desc.checks) {
-        CK(hipMemsetAsync(s->iflags + I_NONFINITE, 0, sizeof(int), st));
-        CK(launch_check_finite(d_x, s->P, s->iflags + I_NONFINITE, st));
-        CK(launch_check_finite(s->targets, 3 * s->n_rays, s->iflags + I_NONFINITE, st));
-        int bad = 0;
-        CK(hipMemcpyAsync(&bad, s->iflags + I_NONFINITE, sizeof(int), hipMemcpyDeviceToHost, st));
-        CK(hipStreamSynchronize(st));
-        if (bad) return fail(PERF_ENUMERIC, "non-finite parameters or targets");
-    }
-    const void* xg = d_x;
-    if (s->xb16) {
-        CK(launch_pack_bf16(d_x, s->xb16, s->P, st));
-        xg = s->xb16;
-    }
-    // 1. gradient b = -J^T r (into vr) and the exact 4x4 blocks, F(x)
-    const int kind = opts->precond;
-    int32_t rc = grad_pass(s, xg, s->vr, s->blocks, true);
-    if (rc != PERF_OK) return rc;
-    CK(hipEventRecord(ev[1], st));
-    // 2. preconditioner
-    int apply_kind = kind;
-    if (kind == PERF_PRECOND_JACOBI || kind == PERF_PRECOND_BLOCK4) {
-        CK(launch_precond_invert(kind, s->blocks, s->units, s->minv, st));
-    } else if (kind == PERF_PRECOND_LEARNED) {
-        rc = learned_minv(s, xg, d_x);
-        if (rc != PERF_OK) return rc;
-    }
-    CK(hipEventRecord(ev[2], st));
-    // 3. PCG (Alg. 2) from Delta_0 = 0 with every scalar on the device
     s->host_scalars[S_MAXITERS] = opts->max_iters;
     s->host_scalars[S_RELTOL] = opts->rel_tol;
     s->host_scalars[S_ABSEPS] = opts->abs_eps;
@@ -595,6 +552,7 @@ int32_t perf_gn_step(perf_scene* s, float* d_x, const perf_pcg_opts* opts, perf_
     CK(launch_pcg_init(apply_kind, s->vr, s->minv, s->vr, s->vz, s->vp, s->vdelta, s->units, s->partials, s->scalars,
                        s->iflags, st));
     const bool poll = opts->rel_tol > 0.0 || opts->abs_eps > 0.0 || opts->stall_ratio > 0.0;
+    int n_jtj = 0;
     for (int it = 0; it < opts->max_iters; ++it) {
         CK(launch_zero(s->vAp, s->P, st, s->iflags + I_DONE));
         RayArgs a = base_args(s);
@@ -602,9 +560,9 @@ int32_t perf_gn_step(perf_scene* s, float* d_x, const perf_pcg_opts* opts, perf_
         a.v = s->vp;
         a.y = s->vAp;
         a.done = s->iflags + I_DONE;
-        CK(hipEventRecord(ev[kPh + 2 * it], st));
+        CK(hipEventRecord(jev[2 * it], st));
         CK(launch_ray(M_JTJ, s->desc.param_dtype, s->geo, a, st));
-        CK(hipEventRecord(ev[kPh + 2 * it + 1], st));
+        CK(hipEventRecord(jev[2 * it + 1], st));
         ++n_jtj;
         CK(launch_pcg_alpha(s->vp, s->vAp, s->units, s->partials, s->scalars, s->hist, s->iflags, st));
         CK(launch_pcg_update(apply_kind, s->minv, s->vdelta, s->vr, s->vz, s->vp, s->vAp, s->units, s->partials,
@@ -620,14 +578,15 @@ int32_t perf_gn_step(perf_scene* s, float* d_x, const perf_pcg_opts* opts, perf_
     CK(hipMemcpyAsync(s->host_scalars, s->scalars, sizeof(double) * S_COUNT, hipMemcpyDeviceToHost, st));
     CK(hipMemcpyAsync(s->host_hist, s->hist, sizeof(double) * 4 * PERF_MAX_PCG, hipMemcpyDeviceToHost, st));
     CK(hipMemcpyAsync(s->host_flags, s->iflags, sizeof(int) * I_COUNT, hipMemcpyDeviceToHost, st));
-    CK(hipEventRecord(ev[3], st));
+    CK(hipEventRecord(ev[0], st));
     CK(hipStreamSynchronize(st));
     const double F0 = s->host_scalars[S_F];
     int flags = s->host_flags[I_FLAGS];
     const int iters = s->host_flags[I_ITERS];
-    // 4. line search (Alg. 3) on F(proj(x + gamma Delta)), capped at ls_max trials
+    // line search (Alg. 3) on F(proj(x + gamma Delta)), capped at ls_max trials
     double gamma = 1.0, mu_acc = F0;
     int trials = 0;
+    int32_t rc;
     if (opts->line_search) {
         const double fac = opts->ls_factor;
         double g = 1.0, mu_prev = INFINITY, best_mu = INFINITY, best_g = 0.0;
@@ -676,19 +635,99 @@ int32_t perf_gn_step(perf_scene* s, float* d_x, const perf_pcg_opts* opts, perf_
         gamma = 1.0;
     }
     if (gamma == 0.0) flags |= PERF_FLAG_NO_DESCENT;
-    CK(hipEventRecord(ev[4], st));
+    CK(hipEventRecord(ev[1], st));
+    out->flags = flags;
+    out->iters = iters;
+    out->trials = trials;
+    out->n_jtj = n_jtj;
+    out->F0 = F0;
+    out->gamma = gamma;
+    out->mu_acc = mu_acc;
+    return PERF_OK;
+}
+
+int32_t perf_gn_step(perf_scene* s, float* d_x, const perf_pcg_opts* opts, perf_gn_stats* stats) {
+    if (!s || !d_x || !opts) return fail(PERF_EINVAL, "null argument");
+    if (!s->targets) return fail(PERF_EINVAL, "scene has no targets");
+    if (opts->max_iters < 1 || opts->max_iters > PERF_MAX_PCG) return fail(PERF_EINVAL, "max_iters must be 1..256");
+    if (opts->precond < PERF_PRECOND_NONE || opts->precond > PERF_PRECOND_LEARNED)
+        return fail(PERF_EINVAL, "bad preconditioner kind");
+    if (opts->line_search && (!(opts->ls_factor > 0.0f && opts->ls_factor < 1.0f) || opts->ls_max < 1))
+        return fail(PERF_EINVAL, "line search needs 0 < ls_factor < 1 and ls_max >= 1");
+    if (opts->precond == PERF_PRECOND_LEARNED && !s->mlp_ready)
+        return fail(PERF_EINVAL, "learned preconditioner has no weights (perf_mlp_set_weights)");
+    hipStream_t st = s->stream;
+    // phase events, plus a pair around every J^T J v launch (its kernel time, for the roofline)
+    constexpr int kPh = 6;
+    hipEvent_t ev[kPh + 2 * PERF_MAX_PCG];
+    const int n_ev = kPh + 2 * opts->max_iters;
+    for (int i = 0; i < n_ev; ++i) CK(hipEventCreate(&ev[i]));
+    struct EvGuard {
+        hipEvent_t* e;
+        int n;
+        ~EvGuard() {
+            for (int i = 0; i < n; ++i) (void)hipEventDestroy(e[i]);
+        }
+    } guard{ev, n_ev};
+    CK(hipEventRecord(ev[0], st));
+    if (s->desc.checks) {
+        CK(hipMemsetAsync(s->iflags + I_NONFINITE, 0, sizeof(int), st));
+        CK(launch_check_finite(d_x, s->P, s->iflags + I_NONFINITE, st));
+        CK(launch_check_finite(s->targets, 3 * s->n_rays, s->iflags + I_NONFINITE, st));
+        int bad = 0;
+        CK(hipMemcpyAsync(&bad, s->iflags + I_NONFINITE, sizeof(int), hipMemcpyDeviceToHost, st));
+        CK(hipStreamSynchronize(st));
+        if (bad) return fail(PERF_ENUMERIC, "non-finite parameters or targets");
+    }
+    const void* xg = d_x;
+    if (s->xb16) {
+        CK(launch_pack_bf16(d_x, s->xb16, s->P, st));
+        xg = s->xb16;
+    }
+    // 1. gradient b = -J^T r (into vr) and the exact 4x4 blocks, F(x)
+    const int kind = opts->precond;
+    int32_t rc = grad_pass(s, xg, s->vr, s->blocks, true);
+    if (rc != PERF_OK) return rc;
+    CK(hipEventRecord(ev[1], st));
+    // 2. preconditioner
+    if (kind == PERF_PRECOND_JACOBI || kind == PERF_PRECOND_BLOCK4) {
+        CK(launch_precond_invert(kind, s->blocks, s->units, s->minv, st));
+    } else if (kind == PERF_PRECOND_LEARNED) {
+        rc = learned_minv(s, xg, d_x);
+        if (rc != PERF_OK) return rc;
+        // keep b for a fallback solve: the feature rows ([units][12] >= P floats) are free now
+        CK(hipMemcpyAsync(s->feat, s->vr, sizeof(float) * s->P, hipMemcpyDeviceToDevice, st));
+    }
+    CK(hipEventRecord(ev[2], st));
+    // 3-4. PCG and the line search
+    SolveOut so;
+    rc = solve_and_search(s, xg, d_x, opts, kind, ev + 3, ev + kPh, &so);
+    if (rc != PERF_OK) return rc;
+    int fallback_iters = 0;
+    if (kind == PERF_PRECOND_LEARNED &&
+        (so.flags & (PERF_FLAG_BREAKDOWN | PERF_FLAG_STALL | PERF_FLAG_NO_DESCENT))) {
+        // the learned solve failed: solve again from Delta_0 = 0 with the exact block inverse
+        fallback_iters = so.iters;
+        CK(hipMemcpyAsync(s->vr, s->feat, sizeof(float) * s->P, hipMemcpyDeviceToDevice, st));
+        CK(launch_precond_invert(PERF_PRECOND_BLOCK4, s->blocks, s->units, s->minv, st));
+        rc = solve_and_search(s, xg, d_x, opts, PERF_PRECOND_BLOCK4, ev + 3, ev + kPh, &so);
+        if (rc != PERF_OK) return rc;
+        so.flags |= PERF_FLAG_FALLBACK;
+    }
     // 5. x <- proj(x + gamma Delta), in place
-    if (gamma != 0.0) CK(launch_trial(d_x, s->vdelta, (float)gamma, s->units, s->geo.nvox, d_x, nullptr, st));
+    if (so.gamma != 0.0) CK(launch_trial(d_x, s->vdelta, (float)so.gamma, s->units, s->geo.nvox, d_x, nullptr, st));
     CK(hipEventRecord(ev[5], st));
     CK(hipEventSynchronize(ev[5]));
     if (stats) {
+        const int iters = so.iters, flags = so.flags;
         memset(stats, 0, sizeof(*stats));
-        stats->F_before = F0;
-        stats->F_after = mu_acc;
-        stats->gamma = gamma;
+        stats->F_before = so.F0;
+        stats->F_after = so.mu_acc;
+        stats->gamma = so.gamma;
         stats->pcg_iters = iters;
-        stats->ls_trials = trials;
+        stats->ls_trials = so.trials;
         stats->flags = flags;
+        stats->fallback_iters = fallback_iters;
         stats->R0 = s->host_scalars[S_R0];
         for (int k = 0; k < iters && k < PERF_MAX_PCG; ++k) {
             stats->alpha[k] = s->host_hist[4 * k + 0];
@@ -704,15 +743,16 @@ int32_t perf_gn_step(perf_scene* s, float* d_x, const perf_pcg_opts* opts, perf_
         }
         CK(hipEventElapsedTime(&ms, ev[0], ev[5]));
         stats->ms_phase[5] = ms;
-        // J^T J v kernel time summed over the launches that did work (the solve's stop flag
-        // turns later launches into immediate exits)
+        // J^T J v kernel time summed over the launches of the final solve that did work (the
+        // solve's stop flag turns later launches into immediate exits)
         float jtj = 0.0f;
-        for (int k = 0; k < n_jtj && k < iters + ((flags & PERF_FLAG_BREAKDOWN) ? 1 : 0); ++k) {
+        const int worked = iters + ((flags & PERF_FLAG_BREAKDOWN) ? 1 : 0);
+        for (int k = 0; k < so.n_jtj && k < worked; ++k) {
             CK(hipEventElapsedTime(&ms, ev[kPh + 2 * k], ev[kPh + 2 * k + 1]));
             jtj += ms;
         }
         stats->ms_phase[6] = jtj;
-        stats->ms_phase[7] = (float)(iters + ((flags & PERF_FLAG_BREAKDOWN) ? 1 : 0));
+        stats->ms_phase[7] = (float)worked;
     }
     return PERF_OK;
 }

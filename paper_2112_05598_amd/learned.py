@@ -207,7 +207,7 @@ def gn_run(sc: Scene, x0, precond: str, n_steps: int, pcg_iters: int, rel_tol: f
     for _ in range(n_steps):
         st = sc.gn_step(x, max_iters=pcg_iters, precond=precond, rel_tol=rel_tol)
         F0 = st["F_before"] if F0 is None else F0
-        iters += st["pcg_iters"]
+        iters += st["pcg_iters"] + st["fallback_iters"]
         F.append(st["F_after"])
         if F_stop >= 0 and st["F_after"] <= F_stop:
             break

@@ -254,7 +254,7 @@ class Scene:
         abi.check(self.lib.perf_gn_step(self.handle, _ptr(x), ctypes.byref(o), ctypes.byref(st)))
         k = st.pcg_iters
         return dict(F_before=st.F_before, F_after=st.F_after, gamma=st.gamma, pcg_iters=k, ls_trials=st.ls_trials,
-                    flags=st.flags, R0=st.R0, R=list(st.R[:k]), alpha=list(st.alpha[:k]),
+                    flags=st.flags, fallback_iters=st.fallback_iters, R0=st.R0, R=list(st.R[:k]), alpha=list(st.alpha[:k]),
                     beta=list(st.beta[:max(k - 1, 0)]), pAp=list(st.pAp[:k + 1]), ms_phase=list(st.ms_phase[:6]), ms_jtj=st.ms_phase[6], n_jtj=int(st.ms_phase[7]))
 
 

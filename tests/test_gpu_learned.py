@@ -211,6 +211,39 @@ def test_learned_gn_step_matches_oracle(setup):
         assert abs(st["F_after"] - ref["F_after"]) <= 1e-3 * ref["F_before"], (st["F_after"], ref["F_after"])
 
 
+def test_failed_learned_solve_falls_back_to_block_jacobi(setup):
+    """A learned solve that stalls is discarded and the step solved again with the exact block
+    inverse, as the oracle's GN step does.  The stall is forced from the host: with a stall
+    ratio of 1e-12 Alg. 2's early exit fires after the first update of either solve."""
+    import oracle
+    from gpu_checks import learned_minv
+    from paper_2112_05598_amd import abi
+    w, orc, sc, targets, t, x = setup
+    bits, _ = learned_weights(7)
+    tx = torch.from_numpy(x).cuda()
+    feat, blocks = sc.features(tx)
+    norm, _ = gpu_norm(feat)
+    sc.mlp_set_weights(torch.from_numpy(bits.view(np.int16)).cuda().view(torch.bfloat16), norm)
+    minv_gpu = learned_minv(sc.mlp_infer(feat, blocks).cpu().numpy())
+    opts = dict(max_iters=6, stall_ratio=1e-12)
+    st = sc.gn_step(tx.clone(), precond="learned", **opts)
+    assert st["flags"] & abi.PERF_FLAG_FALLBACK and st["flags"] & abi.PERF_FLAG_STALL
+    assert st["fallback_iters"] == 1 and st["pcg_iters"] == 1
+    blk = sc.gn_step(tx.clone(), precond="block", **opts)
+    assert not (blk["flags"] & abi.PERF_FLAG_FALLBACK) and blk["fallback_iters"] == 0
+    # the same solve up to the order of the gradient pass's float atomics
+    assert abs(st["alpha"][0] - blk["alpha"][0]) <= 1e-5 * abs(blk["alpha"][0])
+    assert abs(st["F_after"] - blk["F_after"]) <= 1e-5 * blk["F_before"]
+    ref = oracle.gn_step(orc, x.astype(np.float64), targets, precond="learned", learned_minv=minv_gpu,
+                         **opts)
+    assert ref["fallback_iters"] == 1 and ref["pcg"].iters == 1
+    assert abs(st["alpha"][0] - ref["pcg"].alpha[0]) <= 1e-4 * abs(ref["pcg"].alpha[0])
+    assert abs(st["F_after"] - ref["F_after"]) <= 1e-3 * ref["F_before"], (st["F_after"], ref["F_after"])
+    # without a failure the learned solve stands
+    ok = sc.gn_step(tx.clone(), precond="learned", max_iters=6)
+    assert not (ok["flags"] & abi.PERF_FLAG_FALLBACK) and ok["fallback_iters"] == 0
+
+
 def test_fallback_units_take_the_exact_block_inverse(setup):
     """Threshold 0: every touched unit takes the exact block inverse (the block form with t_d
     negated), equal to the oracle's (B + rho I)^-1; a finite threshold: units the FP64 network
