@@ -223,6 +223,7 @@ def gn_compare(w, nets: Dict[str, Model], n_steps=5, pcg_iters=30, rel_tol=0.0, 
     jac = gn_run(sc, x0, "jacobi", n_steps, pcg_iters, rel_tol)
     out = {"seed": w.seed, "pcg_iters_per_step": pcg_iters, "rel_tol": rel_tol, "jacobi": jac}
     msg = f"[learned] GN seed {w.seed}: jacobi {jac['pcg_iters']} it {jac['ms']:.0f} ms F {jac['F'][-1]:.6g}"
+    log(msg + " (running the others)")
     for name, mdl in nets.items():
         pc = "learned"
         if name == "block":
@@ -232,6 +233,8 @@ def gn_compare(w, nets: Dict[str, Model], n_steps=5, pcg_iters=30, rel_tol=0.0, 
         r = gn_run(sc, x0, pc, n_steps + extra_steps, pcg_iters, rel_tol, F_stop=jac["F"][-1])
         r["reached"] = r["F"][-1] <= jac["F"][-1]
         out[name] = r
+        log(f"[learned]   seed {w.seed} {name}: {r['gn_steps']} steps {r['pcg_iters']} it {r['ms']:.0f} ms "
+            f"F {r['F'][-1]:.6g}")
         msg += (f"; {name} {r['gn_steps']} steps {r['pcg_iters']} it {r['ms']:.0f} ms F {r['F'][-1]:.6g}"
                 + ("" if r["reached"] else " (not reached)"))
     log(msg)
