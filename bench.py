@@ -187,9 +187,12 @@ def main():
     elif not args.no_learned and args.precond == "jacobi":
         # GN time-to-residual: the learned preconditioner, from the same start, until it reaches
         # the objective the timed Jacobi steps ended at (same PCG iterations per step)
-        lrn.load_model(device="cuda:0").install(sc)
+        model = lrn.load_model(device="cuda:0")
+        model.install(sc)
         F_target = stats[-1]["F_after"]
         run = lrn.gn_run(sc, x0, "learned", args.steps + 3, args.pcg, F_stop=F_target)
+        del run["x"]
+        frac = [lrn.fallback_fraction(sc, x0), lrn.fallback_fraction(sc, x)]
         print(f"[bench] learned: {run['gn_steps']} GN steps, {run['pcg_iters']} PCG iterations, "
               f"{run['ms']:.0f} ms to F {run['F'][-1]:.6g} (Jacobi: {args.steps} steps, "
               f"{sum(s['pcg_iters'] for s in stats)} iterations, {dt * 1e3:.0f} ms to F {F_target:.6g})",
@@ -198,7 +201,8 @@ def main():
             "target_F": F_target,
             "jacobi": {"gn_steps": args.steps, "pcg_iters": sum(s["pcg_iters"] for s in stats), "ms": dt * 1e3},
             "learned": {"gn_steps": run["gn_steps"], "pcg_iters": run["pcg_iters"], "ms": run["ms"],
-                        "F": run["F"], "reached": run["F"][-1] <= F_target},
+                        "F": run["F"], "reached": run["F"][-1] <= F_target,
+                        "q_fallback": model.q_fallback, "fallback_frac_start_end": frac},
             "model": "paper_2112_05598_amd/weights/precond_mlp.npz"}
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a ray sample", file=sys.stderr, flush=True)

@@ -276,7 +276,7 @@ int32_t perf_invert_blocks(const float* d_blocks, int64_t units, int32_t kind, f
 int32_t perf_pack_bf16(const float* d_in, uint16_t* d_out, int64_t n, void* stream);
 
 /*
- * Learned block preconditioner (per-unit MLP 12 -> 64 -> 64 -> 10, ReLU, BF16 weights on
+ * Learned block preconditioner (per-unit MLP 15 -> 64 -> 64 -> 10, ReLU, BF16 weights on
  * MFMA, FP32 accumulation).  Not in the paper: it replaces the exact 4x4 block inverse of
  * Sec. III-G's diagonal preconditioner by a prediction from cheap per-unit features.
  *
@@ -284,10 +284,12 @@ int32_t perf_pack_bf16(const float* d_in, uint16_t* d_out, int64_t n, void* stre
  *   perf_build_precond) from one traversal at x.  Features per unit: sigma/alpha, colour (3),
  *   log(d + tiny), log(f + tiny), log(1 + sum of sample weights), weighted mean transmittance,
  *   weighted mean colour behind the sample (3), weighted mean sample opacity.
- * The network's input is the standardised feature vector clamp((f - mu) s, -8, 8), with
- *   norm [PERF_MLP_NNORM] = (mu[16], s[16]) FP32 (entries 12..15 of each zero: padding).
+ * The network's input (15 values, padded to 16) is the standardised feature vector
+ *   clamp((f - mu) s, -8, 8), with norm [PERF_MLP_NNORM] = (mu[16], s[16]) FP32 (entries 12..15
+ *   of each zero), followed by the unit's normalised colour-density coupling e~ = e /
+ *   sqrt((d + rho)(f + rho)) from d_blocks (|e~| < 1, not standardised; 0 for an empty unit).
  * perf_mlp_set_weights: d_w device bfloat16 weights in the packed order W1[64][16] b1[64]
- *   W2[64][64] b2[64] W3[16][64] b3[16] (inputs padded 12 -> 16, outputs 10 -> 16 with zeros);
+ *   W2[64][64] b2[64] W3[16][64] b3[16] (inputs padded 15 -> 16, outputs 10 -> 16 with zeros);
  *   n_w must equal PERF_MLP_NW; d_norm the network's standardisation (device FP32); q_fallback:
  *   a unit whose prediction misses its own normalised block B~ by q = ||L L^T B~ - I||_F^2 >
  *   q_fallback takes the exact block inverse instead (plain block-Jacobi as the fallback;

@@ -5,10 +5,12 @@ Not part of the paper: the learned part replaces the exact inverse of each unit'
 per-unit features.  Conventions, identical to the product's:
 
   weights, packed: W1[64][16] b1[64] W2[64][64] b2[64] W3[16][64] b3[16]
-                   (inputs padded 12 -> 16, outputs 10 -> 16 with zeros)
+                   (inputs padded 15 -> 16, outputs 10 -> 16 with zeros)
   standardisation: norm = (mu[16], s[16]) from the training features: mu the mean and
-                   s = 1 / max(std, 1e-3) per feature (0 for the padding); the network's input
-                   is x = clamp((feature - mu) s, -CLAMP, CLAMP)
+                   s = 1 / max(std, 1e-3) per stored feature (0 for the other slots)
+  inputs:          x[0:12] = clamp((feature - mu) s, -CLAMP, CLAMP) for the 12 stored features,
+                   x[12:15] = e~, the normalised colour-density coupling of the unit's block
+                   (the off-diagonal column of B~ below; |e~| < 1, used as is), x[15] = 0
   network:         h1 = relu(W1 x + b1), h2 = relu(W2 h1 + b2), o = W3 h2 + b3
   factor:          L lower triangular from o[0:10] row by row, softplus on the diagonal
   ridge:           rho = 1e-6 max(d, f); D = diag(d, d, d, f) + rho I
@@ -26,6 +28,8 @@ from __future__ import annotations
 import numpy as np
 
 N_IN, N_IN_PAD, N_HID, N_OUT, N_OUT_PAD = 12, 16, 64, 10, 16
+N_CPL = 3               # network inputs taken from the block: the normalised coupling e~
+N_NET = N_IN + N_CPL    # network inputs in use
 SHAPES = [("W1", (N_HID, N_IN_PAD)), ("b1", (N_HID,)), ("W2", (N_HID, N_HID)), ("b2", (N_HID,)),
           ("W3", (N_OUT_PAD, N_HID)), ("b3", (N_OUT_PAD,))]
 NW = sum(int(np.prod(s)) for _, s in SHAPES)
@@ -73,10 +77,10 @@ def pack(p: dict) -> np.ndarray:
 def init_weights(seed: int = 0) -> np.ndarray:
     """He-style initialisation; padded input columns and output rows are zero."""
     rng = np.random.default_rng(seed)
-    p = {"W1": rng.normal(0, np.sqrt(2.0 / N_IN), (N_HID, N_IN_PAD)), "b1": np.zeros(N_HID),
+    p = {"W1": rng.normal(0, np.sqrt(2.0 / N_NET), (N_HID, N_IN_PAD)), "b1": np.zeros(N_HID),
          "W2": rng.normal(0, np.sqrt(2.0 / N_HID), (N_HID, N_HID)), "b2": np.zeros(N_HID),
          "W3": rng.normal(0, np.sqrt(1.0 / N_HID), (N_OUT_PAD, N_HID)), "b3": np.zeros(N_OUT_PAD)}
-    p["W1"][:, N_IN:] = 0.0
+    p["W1"][:, N_NET:] = 0.0
     p["W3"][N_OUT:, :] = 0.0
     p["W3"] *= 0.1
     p["b3"][DIAG] = 0.5413  # softplus(0.5413) = 1: start at L = I, i.e. plain Jacobi
@@ -125,7 +129,16 @@ def standardise(norm: np.ndarray, feat: np.ndarray) -> np.ndarray:
     return x
 
 
-def forward(w: np.ndarray, norm: np.ndarray, feat: np.ndarray, emulate_bf16: bool = False):
+def inputs(norm: np.ndarray, feat: np.ndarray, blocks: np.ndarray) -> np.ndarray:
+    """[n, 16] network inputs: the standardised stored features, then e~ of each unit's block
+    (zero for a unit with no rays or a non-finite block), then one zero."""
+    x = standardise(norm, feat)
+    Bn, _, _ = normalised_block(blocks)
+    x[:, N_IN:N_NET] = Bn[:, 0:3, 3]
+    return x
+
+
+def forward(w: np.ndarray, norm: np.ndarray, feat: np.ndarray, blocks: np.ndarray, emulate_bf16: bool = False):
     """Raw outputs [n, 10] and the activations needed for the backward pass.
 
     emulate_bf16 rounds the input and both hidden activations to bfloat16 before the
@@ -133,7 +146,7 @@ def forward(w: np.ndarray, norm: np.ndarray, feat: np.ndarray, emulate_bf16: boo
     stay exact here)."""
     p = unpack(w)
     rnd = bf16_round if emulate_bf16 else (lambda a: a)
-    x = rnd(standardise(norm, feat))
+    x = rnd(inputs(norm, feat, blocks))
     z1 = x @ p["W1"].T + p["b1"]
     h1 = rnd(np.maximum(z1, 0.0))
     z2 = h1 @ p["W2"].T + p["b2"]
@@ -185,7 +198,7 @@ def minv(w: np.ndarray, norm: np.ndarray, feat: np.ndarray, blocks: np.ndarray, 
     """[n, 4, 4] M^-1 = D^-1/2 L L^T D^-1/2, zero for units with no rays; units whose q exceeds
     q_fallback get the exact block inverse (B + rho I)^-1.  With return_fallback, also the
     [n] mask of those units and their q."""
-    raw, _ = forward(w, norm, feat, emulate_bf16)
+    raw, _ = forward(w, norm, feat, blocks, emulate_bf16)
     L = factor(raw)
     Bn, dis, live = normalised_block(blocks)
     q = prediction_error(L, Bn)
@@ -203,7 +216,7 @@ def loss_and_grad(w: np.ndarray, norm: np.ndarray, feat: np.ndarray, blocks: np.
     units no ray touches) and its gradient w.r.t. the packed weights (the standardisation is
     fixed, not trained)."""
     p = unpack(w)
-    raw, (x, z1, h1, z2, h2) = forward(w, norm, feat)
+    raw, (x, z1, h1, z2, h2) = forward(w, norm, feat, blocks)
     L = factor(raw)
     Bn, _, live = normalised_block(blocks)
     Bn = Bn + damp * np.where(live, 1.0, 0.0)[:, None, None] * np.eye(4)[None]

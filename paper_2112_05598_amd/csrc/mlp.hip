@@ -1,4 +1,4 @@
-// Learned block preconditioner on gfx950: per-unit MLP 12 -> 64 -> 64 -> 10 with bfloat16
+// Learned block preconditioner on gfx950: per-unit MLP 15 -> 64 -> 64 -> 10 with bfloat16
 // operands on the matrix cores (v_mfma_f32_32x32x8_bf16) and FP32 accumulation.
 //
 // Not part of the paper: Sec. III-G preconditions PCG with the diagonal of J^T J; here the
@@ -8,7 +8,8 @@
 // positive definite by construction; D = diag(d, d, d, f) + ridge.
 //
 // The network's input is the standardised feature vector clamp((f - mu) s, -8, 8), with mu and
-// s = 1 / max(std, 1e-3) taken from the training set (norm [32] = mu[16], s[16]).  At inference
+// s = 1 / max(std, 1e-3) taken from the training set (norm [32] = mu[16], s[16]), followed by
+// the normalised colour-density coupling e~ of the unit's block (three values in (-1, 1)).  At inference
 // a unit whose prediction misses its own normalised block by q = ||L L^T B~ - I||_F^2 above a
 // threshold takes the exact block inverse instead (plain block-Jacobi as the fallback).
 //
@@ -31,6 +32,7 @@ typedef float f16v __attribute__((ext_vector_type(16)));
 typedef LDS unsigned short lds_bf;
 
 constexpr int NIN = 12, NIP = 16, NH = 64, NO = 10, NOP = 16;
+constexpr int NNET = NIN + 3;  // network inputs: the stored features, then the block's normalised coupling
 constexpr int OFF_W1 = 0, OFF_B1 = OFF_W1 + NH * NIP, OFF_W2 = OFF_B1 + NH, OFF_B2 = OFF_W2 + NH * NH,
               OFF_W3 = OFF_B2 + NH, OFF_B3 = OFF_W3 + NOP * NH, NW = OFF_B3 + NOP;
 static_assert(NW == PERF_MLP_NW, "packed weight layout");
@@ -179,12 +181,37 @@ __device__ __forceinline__ void make_L(const float raw[NO], float L[4][4]) {
 }
 
 // standardised features of one unit into the X tile row (bf16, zero padded): clamp((f - mu) s)
+// The normalised colour-density coupling e~ = e / sqrt((d + rho)(f + rho)) of a unit's block
+// [d, e (3), f] (|e~| < 1 for a positive semi-definite block); zero for a unit no ray touches or
+// a non-finite block.  In double: d may be subnormal.
+__device__ __forceinline__ void block_coupling(const float* __restrict__ b, float e[3]) {
+    const float d = b[0], f = b[4];
+    const float m = fmaxf(d, f);
+    bool finite = true;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) finite &= isfinite(b[i]);
+    if (!(m > 0.0f) || !finite) {
+        e[0] = e[1] = e[2] = 0.0f;
+        return;
+    }
+    const double rho = (double)kRidge * m;
+    const double s = 1.0 / sqrt(((double)d + rho) * ((double)f + rho));
+#pragma unroll
+    for (int i = 0; i < 3; ++i) e[i] = (float)(b[1 + i] * s);
+}
+
+// one unit's network inputs, rounded to bfloat16: its standardised stored features (clamped),
+// then the coupling of its block as is, then zeros
 __device__ __forceinline__ void load_features(const float* __restrict__ feat, const float* __restrict__ norm,
-                                              int64_t unit, int64_t n, lds_bf* Xrow, lds_bf* Xt, int col) {
+                                              const float* __restrict__ blocks, int64_t unit, int64_t n,
+                                              lds_bf* Xrow, lds_bf* Xt, int col) {
+    float cpl[3] = {0.0f, 0.0f, 0.0f};
+    if (unit < n) block_coupling(blocks + 5 * unit, cpl);
 #pragma unroll
     for (int i = 0; i < NIP; ++i) {
         float v = 0.0f;
         if (unit < n && i < NIN) v = fminf(fmaxf((feat[NIN * unit + i] - norm[i]) * norm[NIP + i], -kClamp), kClamp);
+        else if (unit < n && i < NNET) v = cpl[i - NIN];
         const unsigned short q = f2bf(v);
         Xrow[i] = q;
         if (Xt) Xt[i * LD64 + col] = q;
@@ -217,7 +244,7 @@ __global__ __launch_bounds__(64 * kInferWaves) void k_mlp_infer(const unsigned s
     const int64_t n_tiles = (units + TU - 1) / TU;
     for (int64_t tile = (int64_t)blockIdx.x * kInferWaves + wv; tile < n_tiles; tile += (int64_t)gridDim.x * kInferWaves) {
         const int64_t unit = tile * TU + l;
-        load_features(feat, norm, unit, units, Xs + l * LD16, nullptr, 0);
+        load_features(feat, norm, blocks, unit, units, Xs + l * LD16, nullptr, 0);
         forward_tile(W, Xs, H1s, H2s, Os, nullptr, nullptr);
         if (unit < units) {
             const float* b = blocks + 5 * unit;
@@ -296,7 +323,7 @@ __global__ __launch_bounds__(64) void k_mlp_train(const unsigned short* __restri
     load_weights(w, W, (lds_bf*)sW2t, (lds_bf*)sW3t);
     const int l = lane();
     const int64_t unit = (int64_t)blockIdx.x * TU + l;
-    load_features(feat, norm, unit, n, (lds_bf*)sX + l * LD16, (lds_bf*)sXt, l);
+    load_features(feat, norm, blocks, unit, n, (lds_bf*)sX + l * LD16, (lds_bf*)sXt, l);
     forward_tile(W, (lds_bf*)sX, (lds_bf*)sH1, (lds_bf*)sH2, sO, (lds_bf*)sH1t, (lds_bf*)sH2t);
 
     // robust loss of E = L L^T (B~ + damp I) - I for this unit and its gradient w.r.t. the raw outputs
@@ -457,7 +484,7 @@ __global__ __launch_bounds__(64) void k_mlp_train(const unsigned short* __restri
 #pragma unroll
             for (int v = 0; v < 16; ++v) {
                 const int hh = crow(mb, v), i = ccol(0);
-                if (i < NIN && acc[mb][0][v] != 0.0f) atomicAdd(grad + OFF_W1 + hh * NIP + i, acc[mb][0][v]);
+                if (i < NNET && acc[mb][0][v] != 0.0f) atomicAdd(grad + OFF_W1 + hh * NIP + i, acc[mb][0][v]);
             }
     }
     // bias gradients: row sums of the transposed gradients

@@ -37,7 +37,7 @@ class Model:
 def init_weights(seed: int = 0) -> np.ndarray:
     """He-style initialisation (float64, packed order); the network starts at L = I."""
     rng = np.random.default_rng(seed)
-    nh, ni, nip, no, nop = 64, 12, 16, 10, 16
+    nh, ni, nip, no, nop = 64, 15, 16, 10, 16  # 12 stored features + the block's 3 couplings
     W1 = rng.normal(0, np.sqrt(2.0 / ni), (nh, nip)); W1[:, ni:] = 0.0
     W2 = rng.normal(0, np.sqrt(2.0 / nh), (nh, nh))
     W3 = np.zeros((nop, nh))  # start exactly at L = I: the Jacobi preconditioner
@@ -196,6 +196,15 @@ def load_model(path: str = WEIGHTS, device="cuda:0", q_fallback=None) -> Model:
     return Model(w, nm, q if q_fallback is None else float(q_fallback))
 
 
+def fallback_fraction(sc: Scene, x) -> float:
+    """Share of the touched units whose prediction the installed model's threshold sends to the
+    exact block inverse at x (the library marks them with a negative t_d)."""
+    feat, blocks = sc.features(x)
+    out = sc.mlp_infer(feat, blocks)[:, 0].cpu().numpy()
+    live = np.count_nonzero(out)
+    return float(np.count_nonzero(out < 0) / max(live, 1))
+
+
 def gn_run(sc: Scene, x0, precond: str, n_steps: int, pcg_iters: int, rel_tol: float = 0.0,
            F_stop: float = -1.0) -> dict:
     """Gauss-Newton from x0 with the given preconditioner; stops after n_steps or once F <= F_stop.
@@ -212,7 +221,8 @@ def gn_run(sc: Scene, x0, precond: str, n_steps: int, pcg_iters: int, rel_tol: f
         if F_stop >= 0 and st["F_after"] <= F_stop:
             break
     torch.cuda.synchronize()
-    return {"F0": F0, "F": F, "pcg_iters": iters, "gn_steps": len(F), "ms": (time.perf_counter() - t0) * 1e3}
+    return {"F0": F0, "F": F, "pcg_iters": iters, "gn_steps": len(F), "ms": (time.perf_counter() - t0) * 1e3,
+            "x": x}
 
 
 def gn_compare(w, nets: Dict[str, Model], n_steps=5, pcg_iters=30, rel_tol=0.0, extra_steps=3, log=print) -> dict:
@@ -232,11 +242,16 @@ def gn_compare(w, nets: Dict[str, Model], n_steps=5, pcg_iters=30, rel_tol=0.0, 
             mdl.install(sc)
         r = gn_run(sc, x0, pc, n_steps + extra_steps, pcg_iters, rel_tol, F_stop=jac["F"][-1])
         r["reached"] = r["F"][-1] <= jac["F"][-1]
+        del r["x"]
+        if pc == "learned":
+            r["fallback_frac"] = [fallback_fraction(sc, x0), fallback_fraction(sc, jac["x"])]
         out[name] = r
         log(f"[learned]   seed {w.seed} {name}: {r['gn_steps']} steps {r['pcg_iters']} it {r['ms']:.0f} ms "
-            f"F {r['F'][-1]:.6g}")
+            f"F {r['F'][-1]:.6g}" + (f" fallback {r['fallback_frac'][0]:.3f} at x0, {r['fallback_frac'][1]:.3f} "
+                                     f"at Jacobi's end" if pc == "learned" else ""))
         msg += (f"; {name} {r['gn_steps']} steps {r['pcg_iters']} it {r['ms']:.0f} ms F {r['F'][-1]:.6g}"
                 + ("" if r["reached"] else " (not reached)"))
+    del jac["x"]
     log(msg)
     del sc
     torch.cuda.empty_cache()

@@ -33,7 +33,7 @@ def random_blocks(n, seed):
 
 def unit_errors(mlp, w, feat, blocks, damp):
     """||L L^T (B~ + damp I) - I||_F^2 per unit, assembled independently of loss_and_grad."""
-    L = mlp.factor(mlp.forward(w, unit_norm(mlp), feat)[0])
+    L = mlp.factor(mlp.forward(w, unit_norm(mlp), feat, blocks)[0])
     Bn, _, live = mlp.normalised_block(blocks)
     E = L @ np.transpose(L, (0, 2, 1)) @ (Bn + damp * np.eye(4)) - np.eye(4)
     q = (E * E).sum(axis=(1, 2))
@@ -269,3 +269,24 @@ def test_fallback_units_take_the_exact_block_inverse(mlp, oracle_mod):
     Bn, _, live = mlp.normalised_block(blocks)
     Lx = np.linalg.cholesky(np.linalg.inv(Bn[live]))
     assert mlp.prediction_error(Lx, Bn[live]).max() < 1e-18
+
+
+def test_coupling_inputs_are_the_normalised_off_diagonal(mlp):
+    """Network inputs 12..14 are the block's colour-density coupling scaled to a unit diagonal:
+    for blocks built as e = rho sqrt(d f) u with a unit vector u, that is rho u up to the ridge
+    (1e-6 max(d, f) added to d and f: at most 2.5e-5 relative here, d/f within 50); zero for units
+    no ray touches, and the last input slot stays zero."""
+    rng = np.random.default_rng(8)
+    n = 50
+    d = rng.uniform(0.1, 5.0, n)
+    f = rng.uniform(0.1, 5.0, n)
+    u = rng.normal(size=(n, 3))
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    rho = rng.uniform(0.0, 0.95, n)
+    blocks = np.concatenate([d[:, None], u * (rho * np.sqrt(d * f))[:, None], f[:, None]], axis=1)
+    blocks[:2] = 0.0
+    x = mlp.inputs(unit_norm(mlp), rng.normal(size=(n, 12)), blocks)
+    want = u * rho[:, None]
+    np.testing.assert_allclose(x[2:, 12:15], want[2:], rtol=3e-5, atol=1e-12)
+    assert np.all(x[:2, 12:15] == 0) and np.all(x[:, 15] == 0)
+    assert np.all(np.linalg.norm(x[:, 12:15], axis=1) < 1.0)
