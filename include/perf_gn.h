@@ -276,20 +276,20 @@ int32_t perf_invert_blocks(const float* d_blocks, int64_t units, int32_t kind, f
 int32_t perf_pack_bf16(const float* d_in, uint16_t* d_out, int64_t n, void* stream);
 
 /*
- * Learned block preconditioner (per-unit MLP 15 -> 64 -> 64 -> 10, ReLU, BF16 weights on
+ * Learned block preconditioner (per-unit MLP 9 -> 64 -> 64 -> 10, ReLU, BF16 weights on
  * MFMA, FP32 accumulation).  Not in the paper: it replaces the exact 4x4 block inverse of
  * Sec. III-G's diagonal preconditioner by a prediction from cheap per-unit features.
  *
- * perf_precond_features: d_feat [units][12] FP32 features and d_blocks [units][5] (as in
- *   perf_build_precond) from one traversal at x.  Features per unit: sigma/alpha, colour (3),
- *   log(d + tiny), log(f + tiny), log(1 + sum of sample weights), weighted mean transmittance,
- *   weighted mean colour behind the sample (3), weighted mean sample opacity.
- * The network's input (15 values, padded to 16) is the standardised feature vector
- *   clamp((f - mu) s, -8, 8), with norm [PERF_MLP_NNORM] = (mu[16], s[16]) FP32 (entries 12..15
+ * perf_precond_features: d_feat [units][PERF_MLP_NFEAT] FP32 features and d_blocks [units][5]
+ *   (as in perf_build_precond) from the gradient/block traversal at x; the features come from
+ *   x and the blocks alone (no further traversal): sigma/alpha, colour (3), log(d + 1e-12),
+ *   log(f + 1e-12).  perf_gn_step forms them from the blocks of its own gradient pass.
+ * The network's input (9 values, padded to 16) is the standardised feature vector
+ *   clamp((f - mu) s, -8, 8), with norm [PERF_MLP_NNORM] = (mu[16], s[16]) FP32 (entries 6..15
  *   of each zero), followed by the unit's normalised colour-density coupling e~ = e /
  *   sqrt((d + rho)(f + rho)) from d_blocks (|e~| < 1, not standardised; 0 for an empty unit).
  * perf_mlp_set_weights: d_w device bfloat16 weights in the packed order W1[64][16] b1[64]
- *   W2[64][64] b2[64] W3[16][64] b3[16] (inputs padded 15 -> 16, outputs 10 -> 16 with zeros);
+ *   W2[64][64] b2[64] W3[16][64] b3[16] (inputs padded 9 -> 16, outputs 10 -> 16 with zeros);
  *   n_w must equal PERF_MLP_NW; d_norm the network's standardisation (device FP32); q_fallback:
  *   a unit whose prediction misses its own normalised block B~ by q = ||L L^T B~ - I||_F^2 >
  *   q_fallback takes the exact block inverse instead (plain block-Jacobi as the fallback;
@@ -309,17 +309,18 @@ int32_t perf_pack_bf16(const float* d_in, uint16_t* d_out, int64_t n, void* stre
  *   lr; writes the updated bf16 copy to d_wbf16 and the batch loss to d_loss (device
  *   float[1]).  d_grad_scratch [PERF_MLP_NW] FP32 accumulates the gradient; it must be zero on
  *   entry and is left zero.
- * perf_mlp_feature_stats: d_norm from n rows of features d_feat [n][12]: per-feature mean and
+ * perf_mlp_feature_stats: d_norm from n rows of features d_feat [n][PERF_MLP_NFEAT]: per-feature mean and
  *   s = 1 / max(std, 1e-3), std the population standard deviation, in FP64 and deterministic.
  * perf_mlp_training_rows: training rows from one traversal's features and blocks: every unit
  *   some ray touches (max(d, f) > 0) whose features and block are finite is kept with
  *   probability keep, decided by a hash of
- *   (seed, unit), and the kept rows are written to d_feat_out [cap][12] and d_blocks_out
+ *   (seed, unit), and the kept rows are written to d_feat_out [cap][PERF_MLP_NFEAT] and d_blocks_out
  *   [cap][5] in unit order (deterministic); *n_kept (host) receives the number of kept rows,
  *   of which the first min(n_kept, cap) are written.  Synchronises.
  */
 #define PERF_MLP_NW (64 * 16 + 64 + 64 * 64 + 64 + 16 * 64 + 16)
 #define PERF_MLP_NNORM 32
+#define PERF_MLP_NFEAT 6
 int32_t perf_precond_features(perf_scene* s, const void* d_x, float* d_feat, float* d_blocks);
 int32_t perf_mlp_set_weights(perf_scene* s, const uint16_t* d_w, int32_t n_w, const float* d_norm, float q_fallback);
 int32_t perf_mlp_infer(perf_scene* s, const float* d_feat, const float* d_blocks, float* d_minv);

@@ -9,8 +9,9 @@
                   --stats kernel_stats.csv [--out table.md]
 
 `run` launches, on the named workload at the initial parameters: the J^T J v product `--launches`
-times (seeded random v), the gradient + exact-block pass, the feature pass of the learned
-preconditioner, the MLP inference over every unit and four training steps on 16384 rows; then
+times (seeded random v), the gradient + exact-block pass, the learned preconditioner's features
+(another gradient/block pass and the per-unit feature kernel), the MLP inference over every unit
+and four training steps on 16384 rows; then
 one plain device-to-device copy of `--copy-mib` MiB (an elementwise b = a * 1) as the
 calibration kernel of the HBM counters, and the atomic probe (measure/atomic_probe.hip).  With
 --timing-json it records the durations (HIP events on the launch stream) of an unprofiled run.
@@ -39,7 +40,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))  # the reposi
 KERNEL_SRC = os.path.join(ROOT, "paper_2112_05598_amd", "csrc", "raymarch.hip")
 JTJ_TAG = "k_ray<3, 0>"  # the J^T J v instantiation of k_ray, FP32 parameters
 COPY_TAGS = ("Mul",)  # the calibration copy: b = a * 1 (reads and writes copy-mib MiB)
-KERNELS = {"k_ray<3, 0>": "jtj", "k_ray<4, 0>": "grad", "k_ray<5, 0>": "feat", "k_mlp_infer": "mlp_infer",
+KERNELS = {"k_ray<3, 0>": "jtj", "k_ray<4, 0>": "grad", "k_features": "feat", "k_mlp_infer": "mlp_infer",
            "k_mlp_train": "mlp_train"}
 
 

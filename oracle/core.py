@@ -77,7 +77,6 @@ def _load():
         lib.orc_sample_field.restype = ctypes.c_double
         lib.orc_sample_field.argtypes = [P, P, P, ctypes.c_int]
         lib.orc_ray.argtypes = [P, i64, P, P]
-        lib.orc_feature_sums.argtypes = [P, P, P, i64, P]
         lib.orc_render_image.argtypes = [P, P, ctypes.c_double, P, P, i64, P, P, P]
         lib.orc_jitter_u.restype = ctypes.c_double
         lib.orc_jitter_u.argtypes = [ctypes.c_uint32, i64, ctypes.c_uint32]
@@ -264,14 +263,6 @@ class OracleScene:
         x = _f64(x)
         p = _f64(p)
         return float(self.lib.orc_sample_field(self.p, _ptr(x), _ptr(p), int(ch)))
-
-    def feature_sums(self, x, rays=None):
-        """[units, 6] sums (w, wT, wG (3), w alpha) over every sample corner / texel."""
-        x = _f64(x)
-        r_ids, n = self._rays(rays)
-        out = np.zeros((self.n_units, 6))
-        self.lib.orc_feature_sums(self.p, _ptr(x), _ptr(r_ids), n, _ptr(out))
-        return out
 
     def num_threads(self) -> int:
         return int(self.lib.orc_num_threads())

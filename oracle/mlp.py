@@ -4,13 +4,15 @@ Not part of the paper: the learned part replaces the exact inverse of each unit'
 4x4 block of J^T J (Sec. III-G uses only its diagonal) with a prediction from cheap
 per-unit features.  Conventions, identical to the product's:
 
+  features:        6 per unit, from x and the unit's block alone: sigma/alpha, colour (3),
+                   log d, log f
   weights, packed: W1[64][16] b1[64] W2[64][64] b2[64] W3[16][64] b3[16]
-                   (inputs padded 15 -> 16, outputs 10 -> 16 with zeros)
+                   (inputs padded 9 -> 16, outputs 10 -> 16 with zeros)
   standardisation: norm = (mu[16], s[16]) from the training features: mu the mean and
-                   s = 1 / max(std, 1e-3) per stored feature (0 for the other slots)
-  inputs:          x[0:12] = clamp((feature - mu) s, -CLAMP, CLAMP) for the 12 stored features,
-                   x[12:15] = e~, the normalised colour-density coupling of the unit's block
-                   (the off-diagonal column of B~ below; |e~| < 1, used as is), x[15] = 0
+                   s = 1 / max(std, 1e-3) per feature (0 for the other slots)
+  inputs:          x[0:6] = clamp((feature - mu) s, -CLAMP, CLAMP) for the 6 features,
+                   x[6:9] = e~, the normalised colour-density coupling of the unit's block
+                   (the off-diagonal column of B~ below; |e~| < 1, used as is), x[9:16] = 0
   network:         h1 = relu(W1 x + b1), h2 = relu(W2 h1 + b2), o = W3 h2 + b3
   factor:          L lower triangular from o[0:10] row by row, softplus on the diagonal
   ridge:           rho = 1e-6 max(d, f); D = diag(d, d, d, f) + rho I
@@ -27,7 +29,7 @@ from __future__ import annotations
 
 import numpy as np
 
-N_IN, N_IN_PAD, N_HID, N_OUT, N_OUT_PAD = 12, 16, 64, 10, 16
+N_IN, N_IN_PAD, N_HID, N_OUT, N_OUT_PAD = 6, 16, 64, 10, 16
 N_CPL = 3               # network inputs taken from the block: the normalised coupling e~
 N_NET = N_IN + N_CPL    # network inputs in use
 SHAPES = [("W1", (N_HID, N_IN_PAD)), ("b1", (N_HID,)), ("W2", (N_HID, N_HID)), ("b2", (N_HID,)),
@@ -87,30 +89,21 @@ def init_weights(seed: int = 0) -> np.ndarray:
     return pack(p)
 
 
-def features(x: np.ndarray, sums: np.ndarray, blocks: np.ndarray) -> np.ndarray:
-    """[units, 12]: sigma/alpha, colour (3), log d, log f, log(1 + sum w), mean T,
-    colour behind (sum w G / sum w T, 3), mean alpha."""
+def features(x: np.ndarray, blocks: np.ndarray) -> np.ndarray:
+    """[units, 6]: sigma/alpha, colour (3), log d, log f."""
     x = np.asarray(x, dtype=np.float64).reshape(-1, 4)
-    s = np.asarray(sums, dtype=np.float64)
     b = np.asarray(blocks, dtype=np.float64)
     f = np.zeros((x.shape[0], N_IN))
-    w, wt = s[:, 0], s[:, 1]
-    iw = np.where(w > 0, 1.0 / np.where(w > 0, w, 1.0), 0.0)
-    iwt = np.where(wt > 0, 1.0 / np.where(wt > 0, wt, 1.0), 0.0)
     f[:, 0] = x[:, 3]
     f[:, 1:4] = x[:, 0:3]
     f[:, 4] = np.log(np.maximum(b[:, 0], 0.0) + 1e-12)
     f[:, 5] = np.log(np.maximum(b[:, 4], 0.0) + 1e-12)
-    f[:, 6] = np.log1p(w)
-    f[:, 7] = wt * iw
-    f[:, 8:11] = s[:, 2:5] * iwt[:, None]
-    f[:, 11] = s[:, 5] * iw
     return f
 
 
 def feature_stats(feat: np.ndarray) -> np.ndarray:
     """norm [32] = (mu[16], s[16]) of a training set: per-feature mean and 1 / max(std, 1e-3),
-    std the population standard deviation; zeros for the 4 padding inputs."""
+    std the population standard deviation; zeros for the other slots."""
     f = np.asarray(feat, dtype=np.float64).reshape(-1, N_IN)
     mu = f.mean(axis=0)
     sd = np.sqrt(np.maximum((f * f).mean(axis=0) - mu * mu, 0.0))

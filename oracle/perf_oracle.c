@@ -793,63 +793,3 @@ double orc_sample_field(const orc_scene *s, const double *x, const double p[3], 
 
 int orc_num_threads(void) { return orc_threads(); }
 
-/*
- * Per-unit sums that feed the learned preconditioner's features (not part of the
- * paper's method; test infrastructure for the product's feature pass).  For every
- * sample k and trilinear corner (weight w) of every listed ray:
- *   sums[unit] += (w, w T_k, w G_k (3), w alpha_k),
- * with G_k the colour composited behind sample k (layers and background included,
- * attenuated by the transmittance in front of them); for a texel of layer l with
- * bilinear weight w: (w, w T_l, w T_l S_{l+1} (3), w alpha_l), S_{l+1} the radiance
- * behind the layer.  sums is [units][6], overwritten.
- */
-int orc_feature_sums(const orc_scene *s, const double *x, const int64_t *rays, int64_t n, double *sums) {
-    int64_t U = orc_units(s);
-    int nt = orc_threads();
-    double **buf = (double **)malloc(sizeof(double *) * (size_t)nt);
-    for (int t = 0; t < nt; ++t) buf[t] = (double *)calloc((size_t)(6 * U), sizeof(double));
-    #pragma omp parallel
-    {
-        orc_scratch w; scratch_init(s, &w);
-        double *sb = buf[orc_tid()];
-        #pragma omp for schedule(dynamic, 64)
-        for (int64_t i = 0; i < n; ++i) {
-            double H[3], Te, Tn, tf; int hit;
-            int64_t K = orc_trace(s, x, ray_at(rays, i), w.smp, w.lay, H, &Te, &Tn, &hit, &tf);
-            /* environment, back to front */
-            double S[3] = {s->bg[0], s->bg[1], s->bg[2]};
-            for (int l = s->n_layers - 1; l >= 0; --l) {
-                const orc_layer *e = &w.lay[l];
-                if (!e->used) continue;
-                for (int j = 0; j < 4; ++j) {
-                    double *q = sb + 6 * e->unit[j];
-                    double wj = e->w[j];
-                    q[0] += wj;
-                    q[1] += wj * e->T;
-                    for (int ch = 0; ch < 3; ++ch) q[2 + ch] += wj * e->T * S[ch];
-                    q[5] += wj * e->alpha;
-                }
-                for (int ch = 0; ch < 3; ++ch) S[ch] = e->alpha * e->c[ch] + (1.0 - e->alpha) * S[ch];
-            }
-            /* voxels: G_k behind sample k, from the back */
-            double G[3] = {Te * S[0], Te * S[1], Te * S[2]};
-            for (int64_t k = K - 1; k >= 0; --k) {
-                const orc_sample *q = &w.smp[k];
-                for (int j = 0; j < 8; ++j) {
-                    double *o = sb + 6 * q->idx[j];
-                    double wj = q->w[j];
-                    o[0] += wj;
-                    o[1] += wj * q->T;
-                    for (int ch = 0; ch < 3; ++ch) o[2 + ch] += wj * G[ch];
-                    o[5] += wj * q->alpha;
-                }
-                for (int ch = 0; ch < 3; ++ch) G[ch] += q->T * q->alpha * q->c[ch];
-            }
-        }
-        scratch_free(&w);
-    }
-    reduce_buffers(buf, nt, 6 * U, sums);
-    for (int t = 0; t < nt; ++t) free(buf[t]);
-    free(buf);
-    return 0;
-}

@@ -15,6 +15,7 @@ PERF_MAX_LAYERS = 8
 PERF_MAX_PCG = 256
 PERF_MLP_NW = 64 * 16 + 64 + 64 * 64 + 64 + 16 * 64 + 16
 PERF_MLP_NNORM = 32
+PERF_MLP_NFEAT = 6
 
 PERF_OK, PERF_EINVAL, PERF_ENOMEM, PERF_EDEVICE, PERF_ENUMERIC, PERF_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 PERF_F32, PERF_BF16 = 0, 1

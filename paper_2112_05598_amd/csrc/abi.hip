@@ -4,6 +4,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <string>
 
 #include "perf_internal.h"
@@ -25,7 +26,7 @@ struct perf_scene {
     double* scalars;
     double* hist;
     int* iflags;
-    float *vr, *vz, *vp, *vAp, *vdelta, *vxt, *blocks, *minv, *feat, *featsum;
+    float *vr, *vz, *vp, *vAp, *vdelta, *vxt, *blocks, *minv, *feat;
     uint16_t *xb16, *mlpw;
     float* mlpnorm;
     float q_fallback;
@@ -154,8 +155,8 @@ Layout make_layout(const perf_scene_desc& d, int n_cams) {
     L.minv = take(sizeof(float) * 12 * (size_t)units);  // the largest scaled form (learned: 12 per unit)
     L.xb16 = d.param_dtype == PERF_BF16 ? take(sizeof(uint16_t) * (size_t)P) : 0;
     if (d.learned) {
-        L.feat = take(sizeof(float) * 12 * (size_t)units);
-        L.footprint = take(sizeof(float) * 6 * (size_t)units);  // per-unit feature sums
+        // feature rows; also holds the gradient for a fallback solve, so at least P floats
+        L.feat = take(sizeof(float) * (size_t)std::max(PERF_MLP_NFEAT, 4) * (size_t)units);
         L.mlpw = take(sizeof(uint16_t) * PERF_MLP_NW);
         L.mlpnorm = take(sizeof(float) * PERF_MLP_NNORM);
     }
@@ -228,7 +229,6 @@ int32_t perf_init_scene(const perf_scene_desc* desc, const perf_camera* cams, in
     s->minv = (float*)(s->ws + L.minv);
     s->xb16 = desc->param_dtype == PERF_BF16 ? (uint16_t*)(s->ws + L.xb16) : nullptr;
     s->feat = desc->learned ? (float*)(s->ws + L.feat) : nullptr;
-    s->featsum = desc->learned ? (float*)(s->ws + L.footprint) : nullptr;
     s->mlpw = desc->learned ? (uint16_t*)(s->ws + L.mlpw) : nullptr;
     s->mlpnorm = desc->learned ? (float*)(s->ws + L.mlpnorm) : nullptr;
     s->q_fallback = INFINITY;
@@ -441,21 +441,14 @@ int32_t perf_objective(perf_scene* s, const float* d_x, const float* d_delta, fl
 
 
 // ---------------------------------------------------------------- learned block preconditioner
-static int32_t features_pass(perf_scene* s, const void* xg, const void* xvals, int xdtype, float* feat,
-                             const float* blocks) {
-    CK(launch_zero(s->featsum, 6 * s->units, s->stream));
-    CK(launch_features(s->desc.param_dtype, s->geo, s->cams, xg, s->featsum, s->stream));
-    CK(launch_features_finalize(xvals, xdtype, s->featsum, blocks, s->units, feat, s->stream));
-    return PERF_OK;
-}
-
 int32_t perf_precond_features(perf_scene* s, const void* d_x, float* d_feat, float* d_blocks) {
     if (!s || !d_x || !d_feat) return fail(PERF_EINVAL, "null argument");
-    if (!s->featsum) return fail(PERF_EUNSUPPORTED, "the scene was created without learned = 1");
+    if (!s->feat) return fail(PERF_EUNSUPPORTED, "the scene was created without learned = 1");
     float* blocks = d_blocks ? d_blocks : s->blocks;
     int32_t rc = grad_pass(s, d_x, nullptr, blocks, false);
     if (rc != PERF_OK) return rc;
-    return features_pass(s, d_x, d_x, s->desc.param_dtype, d_feat, blocks);
+    CK(launch_unit_features(d_x, s->desc.param_dtype, blocks, s->units, d_feat, s->stream));
+    return PERF_OK;
 }
 
 int32_t perf_mlp_set_weights(perf_scene* s, const uint16_t* d_w, int32_t n_w, const float* d_norm, float q_fallback) {
@@ -523,10 +516,10 @@ int32_t perf_mlp_training_rows(perf_scene* s, const float* d_feat, const float* 
     return PERF_OK;
 }
 
-// features at x (the blocks of this step are already in s->blocks) and the predicted inverses
-static int32_t learned_minv(perf_scene* s, const void* xg, const float* x32) {
-    int32_t rc = features_pass(s, xg, x32, PERF_F32, s->feat, s->blocks);
-    if (rc != PERF_OK) return rc;
+// features at x from the blocks of this step's gradient pass (in s->blocks) and the predicted
+// inverses: no further traversal
+static int32_t learned_minv(perf_scene* s, const float* x32) {
+    CK(launch_unit_features(x32, PERF_F32, s->blocks, s->units, s->feat, s->stream));
     CK(launch_mlp_infer(s->mlpw, s->mlpnorm, s->q_fallback, s->feat, s->blocks, s->units, s->minv, s->stream));
     return PERF_OK;
 }
@@ -693,9 +686,9 @@ int32_t perf_gn_step(perf_scene* s, float* d_x, const perf_pcg_opts* opts, perf_
     if (kind == PERF_PRECOND_JACOBI || kind == PERF_PRECOND_BLOCK4) {
         CK(launch_precond_invert(kind, s->blocks, s->units, s->minv, st));
     } else if (kind == PERF_PRECOND_LEARNED) {
-        rc = learned_minv(s, xg, d_x);
+        rc = learned_minv(s, d_x);
         if (rc != PERF_OK) return rc;
-        // keep b for a fallback solve: the feature rows ([units][12] >= P floats) are free now
+        // keep b for a fallback solve: the feature rows (at least P floats) are free now
         CK(hipMemcpyAsync(s->feat, s->vr, sizeof(float) * s->P, hipMemcpyDeviceToDevice, st));
     }
     CK(hipEventRecord(ev[2], st));

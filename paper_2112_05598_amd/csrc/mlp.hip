@@ -1,9 +1,10 @@
-// Learned block preconditioner on gfx950: per-unit MLP 15 -> 64 -> 64 -> 10 with bfloat16
+// Learned block preconditioner on gfx950: per-unit MLP 9 -> 64 -> 64 -> 10 with bfloat16
 // operands on the matrix cores (v_mfma_f32_32x32x8_bf16) and FP32 accumulation.
 //
 // Not part of the paper: Sec. III-G preconditions PCG with the diagonal of J^T J; here the
 // exact 4x4 block of each unit (three colours and the opacity) is the training target and
-// the network predicts its inverse from cheap per-unit features.  The output is a lower
+// the network predicts its inverse from cheap per-unit features (the unit's parameters and the
+// diagonals of its block).  The output is a lower
 // triangular factor L (softplus on the diagonal), so M^-1 = D^-1/2 L L^T D^-1/2 is symmetric
 // positive definite by construction; D = diag(d, d, d, f) + ridge.
 //
@@ -31,7 +32,7 @@ typedef float f16v __attribute__((ext_vector_type(16)));
 #define LDS __attribute__((address_space(3)))
 typedef LDS unsigned short lds_bf;
 
-constexpr int NIN = 12, NIP = 16, NH = 64, NO = 10, NOP = 16;
+constexpr int NIN = PERF_MLP_NFEAT, NIP = 16, NH = 64, NO = 10, NOP = 16;
 constexpr int NNET = NIN + 3;  // network inputs: the stored features, then the block's normalised coupling
 constexpr int OFF_W1 = 0, OFF_B1 = OFF_W1 + NH * NIP, OFF_W2 = OFF_B1 + NH, OFF_B2 = OFF_W2 + NH * NH,
               OFF_W3 = OFF_B2 + NH, OFF_B3 = OFF_W3 + NOP * NH, NW = OFF_B3 + NOP;
@@ -551,9 +552,12 @@ __global__ __launch_bounds__(kStatsBlock) void k_feature_stats(const float* __re
         const double var = n > 0 ? fmax(red[1][0] / (double)n - mu * mu, 0.0) : 0.0;
         norm[i] = (float)mu;
         norm[NIP + i] = (float)(1.0 / fmax(sqrt(var), 1e-3));
-        if (i < NIP - NIN) {
-            norm[NIN + i] = 0.0f;
-            norm[NIP + NIN + i] = 0.0f;
+    }
+    // workgroup i also zeroes padding slots NIN + i, NIN + i + NIN, ... of both halves
+    if (threadIdx.x == 0) {
+        for (int j = NIN + i; j < NIP; j += NIN) {
+            norm[j] = 0.0f;
+            norm[NIP + j] = 0.0f;
         }
     }
 }

@@ -62,7 +62,7 @@ enum IFlag { I_DONE = 0, I_ITERS = 1, I_FLAGS = 2, I_NONFINITE = 3, I_COUNT = 16
 // Workspace layout (offsets in bytes from the workspace base).
 struct Layout {
     size_t cams, partials, scalars, hist, iflags;
-    size_t vr, vz, vp, vAp, vdelta, vxt, blocks, minv, xb16, feat, mlpw, mlpnorm, footprint;
+    size_t vr, vz, vp, vAp, vdelta, vxt, blocks, minv, xb16, feat, mlpw, mlpnorm;
     size_t total;
     int64_t n_partials;
 };
@@ -71,7 +71,7 @@ Layout make_layout(const perf_scene_desc& d, int n_cams);
 Geo make_geo(const perf_scene_desc& d, int n_cams);
 
 // ---------------------------------------------------------------- launchers (raymarch.hip)
-enum RayMode { M_RENDER = 0, M_JVP = 1, M_VJP = 2, M_JTJ = 3, M_GRAD = 4, M_FEAT = 5, M_COUNT = 6 };
+enum RayMode { M_RENDER = 0, M_JVP = 1, M_VJP = 2, M_JTJ = 3, M_GRAD = 4, M_COUNT = 5 };
 
 struct RayArgs {
     const DevCam* cams;
@@ -80,11 +80,10 @@ struct RayArgs {
     const float* targets;    // [rays][3] (RENDER residuals / GRAD)
     const float* uin;        // [rays][nres] (VJP)
     float* rout;             // [rays][nres] residuals (RENDER with targets) or u (JVP); [rays][3] H otherwise
-    float* y;                // [P] scatter target (VJP / JTJ), gradient (GRAD), feature sums (FEAT)
+    float* y;                // [P] scatter target (VJP / JTJ), gradient (GRAD)
     float* blocks;           // [units][5] (GRAD)
     double* partials;        // [n_tiles] FP64 sums of r^2
     const int* done;         // skip the launch's work when *done != 0 (PCG stop on device)
-    int32_t* footprint;      // [rays][2] (M_FEAT footprint mode)
     float aux;               // weight lambda of the auxiliary opacity residual (Sec. III-I), 0 = off
     int nres;                // residuals per ray: 4 with the auxiliary residual, else 3
     float thresh;            // RENDER: volume counts as transparent when 1 - T_exit < thresh (0 = off)
@@ -93,8 +92,6 @@ struct RayArgs {
 hipError_t launch_ray(int mode, int param_dtype, const Geo& g, const RayArgs& a, hipStream_t st);
 hipError_t launch_footprint(const Geo& g, const DevCam* cams, int32_t* per_ray, unsigned long long* totals,
                             hipStream_t st);
-hipError_t launch_features(int param_dtype, const Geo& g, const DevCam* cams, const void* x, float* sums,
-                           hipStream_t st);
 
 // ---------------------------------------------------------------- launchers (vector.hip)
 hipError_t launch_zero(float* p, int64_t n, hipStream_t st, const int* done = nullptr);
@@ -114,8 +111,8 @@ hipError_t launch_trial(const float* x, const float* delta, float gamma, int64_t
                         uint16_t* xb16, hipStream_t st);
 hipError_t launch_pack_bf16(const float* in, uint16_t* out, int64_t n, hipStream_t st);
 hipError_t launch_check_finite(const float* p, int64_t n, int* flag, hipStream_t st);
-hipError_t launch_features_finalize(const void* x, int x_dtype, const float* sums, const float* blocks,
-                                    int64_t units, float* feat, hipStream_t st);
+hipError_t launch_unit_features(const void* x, int x_dtype, const float* blocks, int64_t units, float* feat,
+                                hipStream_t st);
 // counts: kVecGrid + 1 int64 of scratch; counts[kVecGrid] receives the number of kept rows
 hipError_t launch_training_rows(const float* feat, const float* blocks, int64_t units, unsigned seed, float keep,
                                 float* feat_out, float* blocks_out, int64_t cap, long long* counts, hipStream_t st);

@@ -626,124 +626,6 @@ struct BrickAtomic {
     }
 };
 
-// The feature pass's accumulator: 6 channels per window voxel (a float4 and a float2 plane),
-// updated like Brick4: quad folds, then elected read-modify-writes in Brick4's corner order.
-struct Brick6 {
-    Window win;
-    int cmask;             // corner-order mirror of the camera (corner_mask)
-    volatile lds_f4* s4;   // [kB3] channels 0..3
-    volatile lds_f2* s2;   // [kB3] channels 4..5
-    volatile lds_u8* tag;  // [kB3] lane ids
-
-    __device__ __forceinline__ void init(f4* base, unsigned char* tb) {
-        s4 = (volatile lds_f4*)base;
-        s2 = (volatile lds_f2*)(base + kB3);
-        tag = (volatile lds_u8*)tb;
-        win.o[0] = win.o[1] = win.o[2] = -(1 << 24);
-        float* f = (float*)base;
-        for (int i = lane_id(); i < 6 * kB3; i += 64) ((volatile lds_float*)f)[i] = 0.0f;
-    }
-    // zero the first n float4 slots of the first plane (the texel table's keys after its flush)
-    __device__ __forceinline__ void clear_head(int n) {
-        for (int i = lane_id(); i < n; i += 64) s4[i] = f4{0.0f, 0.0f, 0.0f, 0.0f};
-    }
-    __device__ __forceinline__ bool inside(const int lo[3], const int hi[3]) const { return win.inside(lo, hi); }
-    template <class F>
-    __device__ __forceinline__ void flush_voxel(const Geo& G, int x, int y, int z, F& out) {
-        const int sl = ring_slot(x, y, z);
-        const f4 a = s4[sl];
-        const f2 b = s2[sl];
-        s4[sl] = f4{0.0f, 0.0f, 0.0f, 0.0f};
-        s2[sl] = f2{0.0f, 0.0f};
-        const float v[6] = {a.x, a.y, a.z, a.w, b.x, b.y};
-        bool nz = false;
-#pragma unroll
-        for (int c = 0; c < 6; ++c) nz |= v[c] != 0.0f;
-        if (nz && x >= 0 && y >= 0 && z >= 0 && x < G.nx && y < G.ny && z < G.nz) out((z * G.ny + y) * G.nx + x, v);
-    }
-    template <class F>
-    __device__ __forceinline__ void flush_all(const Geo& G, F& out) {
-        auto fl = [&](int x, int y, int z) { flush_voxel(G, x, y, z, out); };
-        win.each_voxel(fl);
-    }
-    template <class F>
-    __device__ __forceinline__ void fit(const Geo& G, bool on, const int lo[3], const int hi[3], F& out) {
-        auto fl = [&](int x, int y, int z) { flush_voxel(G, x, y, z, out); };
-        win.fit(on, lo, hi, fl);
-    }
-    // add w_i * base to the 8 corners of every lane that is on (uniform call)
-    template <class Sink>
-    __device__ __forceinline__ void scatter8(const Geo& G, bool on, bool inb, const Corners& c, const float base[6],
-                                             Sink& out) {
-        if (wave_any(on && !inb)) {
-            if (on && !inb) {
-#pragma unroll
-                for (int i = 0; i < 8; ++i) {
-                    const int x = c.i[0] + (i & 1), y = c.i[1] + ((i >> 1) & 1), z = c.i[2] + (i >> 2);
-                    float vv[6];
-#pragma unroll
-                    for (int q = 0; q < 6; ++q) vv[q] = base[q] * c.w[i];
-                    out((z * G.ny + y) * G.nx + x, vv);
-                }
-            }
-        }
-        const bool mine = on && inb;
-        if (!wave_any(mine)) return;
-        const int lid = lane_id();
-        const unsigned char lane = (unsigned char)lid;
-        // fold the quad's lanes that share a cell, as the J^T scatter does (same swaps, same
-        // corner order for the lanes of a 2x2 quad)
-        const QuadFolds q = quad_folds(mine, c.v);
-        const int phi = ((((lid & 7) >> 1) << 1) + (lid >> 4)) & 7;
-        const int sx0 = c.i[0] & 7, sx1 = (c.i[0] + 1) & 7;
-        const int sy0 = (c.i[1] & 7) << 3, sy1 = ((c.i[1] + 1) & 7) << 3;
-        const int sz0 = (c.i[2] & 7) << 6, sz1 = ((c.i[2] + 1) & 7) << 6;
-        const float wx0 = 1.0f - c.f[0], wy0 = 1.0f - c.f[1], wz0 = 1.0f - c.f[2];
-#pragma unroll 1
-        for (int r = 0; r < 8; ++r) {
-            const int i = ((r + phi) & 7) ^ cmask;
-            const bool bx = i & 1, by = i & 2, bz = i & 4;
-            const int sl = (bz ? sz1 : sz0) + (by ? sy1 : sy0) + (bx ? sx1 : sx0);
-            const float w = mine ? (bx ? c.f[0] : wx0) * (by ? c.f[1] : wy0) * (bz ? c.f[2] : wz0) : 0.0f;
-            f4 a;
-            f2 b;
-            {
-#pragma clang fp contract(off)
-                a = f4{base[0], base[1], base[2], base[3]} * w;
-                b = f2{base[4], base[5]} * w;
-                const f4 z4 = f4{0.0f, 0.0f, 0.0f, 0.0f};
-                const f2 z2 = f2{0.0f, 0.0f};
-                const f4 ga = q.give_x ? a : z4;
-                const f2 gb = q.give_x ? b : z2;
-                a += dpp_xor1(ga);
-                b += f2{dpp_xor1(gb.x), dpp_xor1(gb.y)};
-                const f4 ha = q.give_y ? a : z4;
-                const f2 hb = q.give_y ? b : z2;
-                a += dpp_row_xor8(ha);
-                b += f2{dpp_row_xor8(hb.x), dpp_row_xor8(hb.y)};
-                const f4 da = q.give_d ? a : z4;
-                const f2 db = q.give_d ? b : z2;
-                a += dpp_row_xor8(dpp_xor1(da));
-                b += f2{dpp_row_xor8(dpp_xor1(db.x)), dpp_row_xor8(dpp_xor1(db.y))};
-            }
-            bool pend = q.keep;
-            while (wave_any(pend)) {
-                if (pend) {
-                    tag[sl] = lane;
-                    const unsigned char t = tag[sl];
-                    const f4 c4 = s4[sl];
-                    const f2 c2 = s2[sl];
-                    if (t == lane) {
-                        s4[sl] = c4 + a;
-                        s2[sl] = c2 + b;
-                        pend = false;
-                    }
-                }
-            }
-        }
-    }
-};
-
 __device__ __forceinline__ int __hip_atomic_compare_exchange_strong_ret(lds_int* p, int expected, int desired) {
     __hip_atomic_compare_exchange_strong(p, &expected, desired, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
                                          __HIP_MEMORY_SCOPE_WAVEFRONT);
@@ -817,16 +699,6 @@ struct SinkGrad {  // grad[4u + c] (c < 4) and blocks[5u + c] (channels 4..8)
         }
     }
 };
-struct SinkFeat {  // sums[6u + c]
-    float* sums;
-    __device__ __forceinline__ void operator()(int u, const float* v) const {
-        float* p = sums + 6 * (size_t)u;
-#pragma unroll
-        for (int c = 0; c < 6; ++c)
-            if (v[c] != 0.0f) atomic_add(p + c, v[c]);
-    }
-};
-
 // ------------------------------------------------------------------ forward pass (+ tangent)
 // Optical depth in front of a sample, summed with compensation (Kahan) so that the
 // adjoint pass can step it back sample by sample with an error of order eps * V_total.
@@ -1344,79 +1216,6 @@ __device__ __forceinline__ void grad_scatter(const Geo& G, const Ray& r, bool li
     B.flush_all(G, sink);
 }
 
-// ------------------------------------------------------------------ features for the learned preconditioner
-// Per sample and corner (weight w): (w, w T, w G (3), w alpha), G the colour composited
-// behind the sample (attenuated); for a texel, T_l and T_l S (S behind the layer).
-template <int PD>
-__device__ __forceinline__ void feature_scatter(const Geo& G, const Ray& r, bool live, XL<PD> X, Depth depth,
-                                                Brick6& B, TexTable<6>& TT, float* __restrict__ sums) {
-    SinkFeat sink{sums};
-    const float Tx = exp_neg(depth.value());
-    float S[3] = {0.0f, 0.0f, 0.0f};
-    if (live) {
-        auto emit = [&](const Tex& tx, const float c[3], float al, float Tl, const float Sb[3]) {
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const float w = tx.w[j];
-                if (w == 0.0f) continue;
-                const float v[6] = {w, w * Tl, w * Tl * Sb[0], w * Tl * Sb[1], w * Tl * Sb[2], w * al};
-                TT.insert(tx.t[j], v, sink);
-            }
-        };
-        env_back<PD>(G, r, X, Tx, S, emit);
-    }
-    TT.flush(sink);
-    B.clear_head(16);  // the table's keys (its sums are left at zero by the flush)
-    float G0 = Tx * S[0], G1 = Tx * S[1], G2 = Tx * S[2];
-    const int nx = G.nx, nxy = G.nx * G.ny;
-    const float unit = G.h * G.step;
-    const float t_max = wave_max_f(r.K > 0 ? r.tf : -INFINITY);
-    const int off = r.K > 0 ? (int)((t_max - r.tf) / unit + 0.5f) : 0;
-    const int J = wave_max_i(r.K > 0 ? off + r.K : 0);
-    for (int j = 0; j < J; ++j) {
-        const int m = j - off;
-        const bool on = m >= 0 && m < r.K;
-        const int k = r.K - 1 - m;
-        Corners c{};
-        float dk = 0.0f;
-        int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
-        if (on) {
-            float g[3];
-            dk = sample_at(G, r, k, g);
-            corners(G, g, c);
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                lo[a] = c.i[a];
-                hi[a] = c.i[a] + 1;
-            }
-        }
-        B.fit(G, on, lo, hi, sink);
-        float base6[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-        float A = 0.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
-        if (on) {
-            float sg;
-            gather<PD>(X, c, nx, nxy, sg, c0, c1, c2);
-            const float tau = sg * dk;
-            depth.add(-tau);
-            const float T = (k == 0) ? 1.0f : exp_neg(depth.value());
-            const float al = one_minus_exp_neg(tau, exp_neg(tau));
-            A = T * al;
-            base6[0] = 1.0f;
-            base6[1] = T;
-            base6[2] = G0;
-            base6[3] = G1;
-            base6[4] = G2;
-            base6[5] = al;
-        }
-        // every lane takes part (the scatter swaps registers between lanes)
-        B.scatter8(G, on, on && B.inside(lo, hi), c, base6, sink);
-        G0 += A * c0;
-        G1 += A * c1;
-        G2 += A * c2;
-    }
-    B.flush_all(G, sink);
-}
-
 // ------------------------------------------------------------------ workgroup FP64 sum
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -1461,8 +1260,8 @@ __device__ __forceinline__ Pix pixel_of(const Geo& G) {
 
 template <int MODE>
 struct Lds {
-    static constexpr int NCH = MODE == M_GRAD ? 9 : (MODE == M_FEAT ? 6 : 4);
-    static constexpr bool SCATTER = MODE == M_VJP || MODE == M_JTJ || MODE == M_GRAD || MODE == M_FEAT;
+    static constexpr int NCH = MODE == M_GRAD ? 9 : 4;
+    static constexpr bool SCATTER = MODE == M_VJP || MODE == M_JTJ || MODE == M_GRAD;
 };
 
 template <int MODE, int PD>
@@ -1556,7 +1355,7 @@ __global__ __launch_bounds__(kBlock) void k_ray(Geo G, RayArgs A) {
             // added to the sigma partial of every sample
             const float q4 = -u4 * dr4 * Texit;
             adjoint_scatter<PD>(G, r, p.active, X, u, q4, depth, B, TT, A.y);
-        } else if constexpr (MODE == M_GRAD) {
+        } else {
             BrickAtomic<NCH> B;
             B.init((float*)(s_brick + wave * NCH * kB3 / 4));
             TT.init((int*)(s_brick + wave * NCH * kB3 / 4), (float*)(s_brick + wave * NCH * kB3 / 4) + 64);
@@ -1572,12 +1371,6 @@ __global__ __launch_bounds__(kBlock) void k_ray(Geo G, RayArgs A) {
             // the auxiliary residual's row: d r4 / d sigma_k = g4 delta_k
             const float g4 = -dr4 * Texit;
             grad_scatter<PD>(G, r, p.active, X, res, p.active ? r4 : 0.0f, g4, depth, B, TT, A.y, A.blocks);
-        } else {
-            Brick6 B;
-            B.init(s_brick + wave * NCH * kB3 / 4, s_tag + wave * kB3);
-            TT.init((int*)(s_brick + wave * NCH * kB3 / 4), (float*)(s_brick + wave * NCH * kB3 / 4) + 64);
-            B.cmask = corner_mask(A.cams[p.cam]);
-            feature_scatter<PD>(G, r, p.active, X, depth, B, TT, A.y);
         }
     }
     if constexpr (MODE == M_RENDER || MODE == M_GRAD) {
@@ -1657,7 +1450,6 @@ hipError_t launch_mode(int mode, const Geo& g, const RayArgs& a, hipStream_t st)
         case M_VJP: return launch_one<M_VJP, PD>(g, a, st);
         case M_JTJ: return launch_one<M_JTJ, PD>(g, a, st);
         case M_GRAD: return launch_one<M_GRAD, PD>(g, a, st);
-        case M_FEAT: return launch_one<M_FEAT, PD>(g, a, st);
         default: return hipErrorInvalidValue;
     }
 }
@@ -1675,15 +1467,6 @@ hipError_t launch_footprint(const Geo& g, const DevCam* cams, int32_t* per_ray, 
     if (grid == 0) return hipSuccess;
     hipLaunchKernelGGL(k_footprint, dim3(grid), dim3(kBlock), 0, st, g, cams, per_ray, totals);
     return hipGetLastError();
-}
-
-hipError_t launch_features(int param_dtype, const Geo& g, const DevCam* cams, const void* x, float* sums,
-                           hipStream_t st) {
-    RayArgs a{};
-    a.cams = cams;
-    a.x = x;
-    a.y = sums;
-    return launch_ray(M_FEAT, param_dtype, g, a, st);
 }
 
 }  // namespace perf

@@ -343,11 +343,12 @@ __global__ void k_check_finite(const float* __restrict__ p, int64_t n, int* flag
     if (bad) atomicOr(flag, 1);
 }
 
-// features [units][12] from the parameters, the per-unit sums and the blocks
+// features [units][PERF_MLP_NFEAT] from the parameters and the blocks of the gradient pass:
+// sigma/alpha, colour (3), log d, log f
 __device__ __forceinline__ float bf16f(unsigned short b) { return __uint_as_float(((unsigned)b) << 16); }
 
-__global__ void k_features(const void* __restrict__ xp, int x_bf16, const float* __restrict__ sums,
-                           const float* __restrict__ blocks, int64_t units, float* __restrict__ feat) {
+__global__ void k_features(const void* __restrict__ xp, int x_bf16, const float* __restrict__ blocks, int64_t units,
+                           float* __restrict__ feat) {
     for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < units; u += (int64_t)gridDim.x * blockDim.x) {
         float4 xv;
         if (x_bf16) {
@@ -356,26 +357,14 @@ __global__ void k_features(const void* __restrict__ xp, int x_bf16, const float*
         } else {
             xv = reinterpret_cast<const float4*>(xp)[u];
         }
-        const float* s = sums + 6 * u;
         const float* b = blocks + 5 * u;
-        // the means divide sums that can be far below the FP32 normal range (units seen only
-        // through near-opaque matter): in double
-        const float w = s[0];
-        const double iw = w > 0.0f ? 1.0 / (double)w : 0.0;
-        const double iwt = s[1] > 0.0f ? 1.0 / (double)s[1] : 0.0;
-        float* f = feat + 12 * u;
+        float* f = feat + PERF_MLP_NFEAT * u;
         f[0] = xv.w;
         f[1] = xv.x;
         f[2] = xv.y;
         f[3] = xv.z;
         f[4] = logf(fmaxf(b[0], 0.0f) + 1e-12f);
         f[5] = logf(fmaxf(b[4], 0.0f) + 1e-12f);
-        f[6] = log1pf(w);
-        f[7] = (float)(s[1] * iw);
-        f[8] = (float)(s[2] * iwt);  // colour behind, unattenuated: sum w G / sum w T
-        f[9] = (float)(s[3] * iwt);
-        f[10] = (float)(s[4] * iwt);
-        f[11] = (float)(s[5] * iw);
     }
 }
 
@@ -401,7 +390,7 @@ __device__ __forceinline__ bool keep_row(const float* __restrict__ feat, const f
 #pragma unroll
     for (int i = 0; i < 5; ++i) ok &= isfinite(b[i]);
 #pragma unroll
-    for (int i = 0; i < 12; ++i) ok &= isfinite(feat[12 * u + i]);
+    for (int i = 0; i < PERF_MLP_NFEAT; ++i) ok &= isfinite(feat[PERF_MLP_NFEAT * u + i]);
     return ok && mix32(seed ^ mix32((unsigned)u ^ (unsigned)(u >> 32) * 0x9e3779b9u)) < thresh;
 }
 
@@ -465,7 +454,7 @@ __global__ __launch_bounds__(kVecBlock) void k_rows_write(const float* __restric
         const long long dst = at + before;
         if (k && dst < cap) {
 #pragma unroll
-            for (int i = 0; i < 12; ++i) feat_out[12 * dst + i] = feat[12 * u + i];
+            for (int i = 0; i < PERF_MLP_NFEAT; ++i) feat_out[PERF_MLP_NFEAT * dst + i] = feat[PERF_MLP_NFEAT * u + i];
 #pragma unroll
             for (int i = 0; i < 5; ++i) blocks_out[5 * dst + i] = blocks[5 * u + i];
         }
@@ -615,10 +604,10 @@ hipError_t launch_training_rows(const float* feat, const float* blocks, int64_t 
     return hipGetLastError();
 }
 
-hipError_t launch_features_finalize(const void* x, int x_dtype, const float* sums, const float* blocks,
-                                    int64_t units, float* feat, hipStream_t st) {
+hipError_t launch_unit_features(const void* x, int x_dtype, const float* blocks, int64_t units, float* feat,
+                                hipStream_t st) {
     hipLaunchKernelGGL(k_features, dim3(grid_for(units)), dim3(kVecBlock), 0, st, x, x_dtype == PERF_BF16 ? 1 : 0,
-                       sums, blocks, units, feat);
+                       blocks, units, feat);
     return hipGetLastError();
 }
 

@@ -37,7 +37,7 @@ class Model:
 def init_weights(seed: int = 0) -> np.ndarray:
     """He-style initialisation (float64, packed order); the network starts at L = I."""
     rng = np.random.default_rng(seed)
-    nh, ni, nip, no, nop = 64, 15, 16, 10, 16  # 12 stored features + the block's 3 couplings
+    nh, ni, nip, no, nop = 64, 9, 16, 10, 16  # 6 features + the block's 3 couplings
     W1 = rng.normal(0, np.sqrt(2.0 / ni), (nh, nip)); W1[:, ni:] = 0.0
     W2 = rng.normal(0, np.sqrt(2.0 / nh), (nh, nh))
     W3 = np.zeros((nop, nh))  # start exactly at L = I: the Jacobi preconditioner
@@ -57,7 +57,7 @@ def scene_for(workload, device="cuda:0", learned=True):
 
 def generate(workloads, gn_steps=5, per_step=65536, pcg_iters=5, seed=0, log=print, first_step=0):
     """Features and blocks along Jacobi-GN trajectories (steps first_step .. gn_steps - 1 are
-    sampled, about per_step touched units each): (feat [n, 12], blocks [n, 5]) GPU tensors."""
+    sampled, about per_step touched units each): (feat [n, PERF_MLP_NFEAT], blocks [n, 5]) GPU tensors."""
     feats, blocks = [], []
     for w in workloads:
         sc = scene_for(w)

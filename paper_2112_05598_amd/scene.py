@@ -196,13 +196,14 @@ class Scene:
 
     # ------------------------------------------------------------ learned preconditioner
     def features(self, x):
-        """(features [units, 12], exact blocks [units, 5]) at x."""
+        """(features [units, PERF_MLP_NFEAT], exact blocks [units, 5]) at x: one gradient/block
+        traversal; the features come from x and the blocks."""
         self._check_params(x)
         self._bind()
-        feat = torch.empty(self.n_units * 12, dtype=torch.float32, device=self.device)
+        feat = torch.empty(self.n_units * abi.PERF_MLP_NFEAT, dtype=torch.float32, device=self.device)
         blocks = torch.empty(self.n_units * 5, dtype=torch.float32, device=self.device)
         abi.check(self.lib.perf_precond_features(self.handle, _ptr(x), _ptr(feat), _ptr(blocks)))
-        return feat.view(-1, 12), blocks.view(-1, 5)
+        return feat.view(-1, abi.PERF_MLP_NFEAT), blocks.view(-1, 5)
 
     def mlp_set_weights(self, w_bf16: torch.Tensor, norm: torch.Tensor, q_fallback: float = float("inf")):
         """Network weights (bfloat16 [PERF_MLP_NW]), standardisation (float32 [PERF_MLP_NNORM]) and
@@ -218,11 +219,11 @@ class Scene:
                                                 ctypes.c_float(q_fallback)))
 
     def training_rows(self, feat: torch.Tensor, blocks: torch.Tensor, seed: int, keep: float, cap: int):
-        """(features [k, 12], blocks [k, 5], n_kept) for a random subset of the touched units
+        """(features [k, PERF_MLP_NFEAT], blocks [k, 5], n_kept) for a random subset of the touched units
         (library-side sampling: each kept with probability keep; at most cap rows written, unit
         order; cap = 0 only counts)."""
         self._bind()
-        fo = torch.empty(max(cap, 1) * 12, dtype=torch.float32, device=self.device)
+        fo = torch.empty(max(cap, 1) * abi.PERF_MLP_NFEAT, dtype=torch.float32, device=self.device)
         bo = torch.empty(max(cap, 1) * 5, dtype=torch.float32, device=self.device)
         n = ctypes.c_int64()
         abi.check(self.lib.perf_mlp_training_rows(self.handle, _ptr(feat.contiguous()), _ptr(blocks.contiguous()),
@@ -230,7 +231,7 @@ class Scene:
                                                   _ptr(fo) if cap else None, _ptr(bo) if cap else None, cap,
                                                   ctypes.byref(n)))
         k = min(n.value, cap)
-        return fo.view(-1, 12)[:k], bo.view(-1, 5)[:k], n.value
+        return fo.view(-1, abi.PERF_MLP_NFEAT)[:k], bo.view(-1, 5)[:k], n.value
 
     def mlp_infer(self, feat: torch.Tensor, blocks: torch.Tensor):
         """[units, 12] predicted block inverses in scaled form (t_d, t_f, L row by row)."""
@@ -260,7 +261,7 @@ class Scene:
 
 def mlp_train_step(w32, wbf16, m, v, t: int, lr: float, norm, feat, blocks, loss, grad, stream=None,
                    damp: float = 0.0):
-    """One Adam step of the learned preconditioner on a batch (feat [n,12], blocks [n,5]) with the
+    """One Adam step of the learned preconditioner on a batch (feat [n, PERF_MLP_NFEAT], blocks [n, 5]) with the
     fixed standardisation norm [32]; the target is the damped normalised inverse (B~ + damp I)^-1."""
     lib = abi.load()
     n = int(feat.shape[0])
@@ -271,10 +272,11 @@ def mlp_train_step(w32, wbf16, m, v, t: int, lr: float, norm, feat, blocks, loss
 
 
 def mlp_feature_stats(feat: torch.Tensor, stream=None) -> torch.Tensor:
-    """Standardisation [32] = (mu[16], s[16]) of a training set of features [n, 12] (library-side)."""
+    """Standardisation [32] = (mu[16], s[16]) of a training set of features [n, PERF_MLP_NFEAT]
+    (library-side)."""
     lib = abi.load()
-    if feat.dtype != torch.float32 or not feat.is_cuda or feat.dim() != 2 or feat.shape[1] != 12:
-        raise ValueError("features must be a float32 device tensor of shape [n, 12]")
+    if feat.dtype != torch.float32 or not feat.is_cuda or feat.dim() != 2 or feat.shape[1] != abi.PERF_MLP_NFEAT:
+        raise ValueError(f"features must be a float32 device tensor of shape [n, {abi.PERF_MLP_NFEAT}]")
     out = torch.empty(abi.PERF_MLP_NNORM, dtype=torch.float32, device=feat.device)
     st = ctypes.c_void_p(torch.cuda.current_stream(feat.device).cuda_stream) if stream is None else stream
     abi.check(lib.perf_mlp_feature_stats(_ptr(feat.contiguous()), feat.shape[0], _ptr(out), st))

@@ -36,6 +36,16 @@ def test_every_declared_symbol_is_exported(lib):
     assert names == {s[0] for s in abi.SIGNATURES}
 
 
+def test_binding_constants_match_the_header():
+    """The binding's sizes are the header's #defines (the ABI's array sizes and row widths)."""
+    from paper_2112_05598_amd import abi
+    text = open(os.path.join(ROOT, "include", "perf_gn.h")).read()
+    defs = dict(re.findall(r"#define[ \t]+(PERF_[A-Z0-9_]+)[ \t]+(.+)", text))
+    assert len(defs) >= 5
+    for name, expr in defs.items():
+        assert getattr(abi, name) == eval(expr, {}), name
+
+
 def _desc(**kw):
     import perf_synth as ps
     from paper_2112_05598_amd.scene import make_desc

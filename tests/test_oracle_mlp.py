@@ -45,7 +45,7 @@ def unit_errors(mlp, w, feat, blocks, damp):
 def test_loss_gradient_matches_finite_differences(mlp, damp):
     rng = np.random.default_rng(0)
     w = mlp.init_weights(1) + 0.05 * rng.normal(size=mlp.NW)
-    feat = rng.normal(size=(40, 12))
+    feat = rng.normal(size=(40, mlp.N_IN))
     blocks = random_blocks(40, 2)
     q = unit_errors(mlp, w, feat, blocks, damp)
     # both branches of the robust loss are exercised
@@ -88,7 +88,7 @@ def test_damped_inverse_is_a_zero_of_the_loss(mlp, damp):
         p["W3"][:] = 0.0
         p["b3"][:] = 0.0
         p["b3"][:10] = mlp.raw_from_factor(L[u:u + 1])[0]
-        loss, g = mlp.loss_and_grad(mlp.pack(p), unit_norm(mlp), np.zeros((1, 12)), blocks[u:u + 1], damp)
+        loss, g = mlp.loss_and_grad(mlp.pack(p), unit_norm(mlp), np.zeros((1, mlp.N_IN)), blocks[u:u + 1], damp)
         assert loss < 1e-20
         assert np.abs(g).max() < 1e-9
 
@@ -118,7 +118,7 @@ def test_initial_network_is_jacobi(mlp, oracle_mod):
     p["W3"][:] = 0.0
     w = mlp.pack(p)
     blocks = random_blocks(20, 6)
-    feat = np.random.default_rng(1).normal(size=(20, 12))
+    feat = np.random.default_rng(1).normal(size=(20, mlp.N_IN))
     M = mlp.minv(w, unit_norm(mlp), feat, blocks)
     sp = np.logaddexp(0.0, 0.5413)
     b = blocks
@@ -139,31 +139,12 @@ def test_bf16_rounding(mlp):
     np.testing.assert_array_equal(mlp.bits_to_f64(mlp.bf16_bits(v)), r)
 
 
-def test_feature_sums_identities(oracle_mod):
-    """Sum over units of the weight channel = samples + layers hit (weights of a lookup sum
-    to 1); of the transmittance channel = sum over rays of T at every sample and layer."""
-    w = ps.workload("tiny")
-    sc = oracle_mod.OracleScene(w.spec, w.cams)
-    x = w.x_gt.astype(np.float64)
-    sums = sc.feature_sums(x)
-    U, L, K = sc.footprint()
-    assert abs(sums[:, 0].sum() - (K.sum() + L.sum())) < 1e-9 * (K.sum() + L.sum())
-    totT = 0.0
-    for ray in range(sc.n_rays):
-        s = sc.ray_samples(x, ray)
-        totT += s["T"].sum()
-    # layer transmittances: T in front of each used layer
-    H, _, _, Te = sc.render(x)
-    assert sums[:, 1].sum() >= totT - 1e-9
-    assert np.all(sums[:, 0] >= 0) and np.all(sums[:, 1] <= sums[:, 0] + 1e-12)
-
-
 def test_learned_inverse_scales_with_the_block(mlp):
     """M^-1 = D^-1/2 L L^T D^-1/2 with B~ = D^-1/2 B D^-1/2 scale-free: scaling a block by s scales
     the predicted inverse by 1/s exactly, at any s (no threshold on tiny diagonals)."""
     w = mlp.init_weights(5)
     blocks = random_blocks(6, 8)
-    feat = np.random.default_rng(2).normal(size=(6, 12))
+    feat = np.random.default_rng(2).normal(size=(6, mlp.N_IN))
     M1 = mlp.minv(w, unit_norm(mlp), feat, blocks)
     for s in (1e-20, 1e-41):
         Ms = mlp.minv(w, unit_norm(mlp), feat, blocks * s)
@@ -173,78 +154,33 @@ def test_learned_inverse_scales_with_the_block(mlp):
     assert np.all(np.linalg.eigvalsh(M1[3:]) > 0)
 
 
-def test_feature_sums_axis_ray_closed_form(oracle_mod):
-    """Every channel of the feature sums on a ray along -x through voxel centres of a uniform
-    medium, written out in closed form: samples at the step midpoints, trilinear weights
-    max(0, 1 - |g - i|) along x (clamped to the edge) and 1 on the centre voxel in y and z,
-    T_k = exp(-sigma delta k), alpha = 1 - exp(-sigma delta), G_k = sum_{m>k} T_m alpha c +
-    T_end S with S the layer seen in front of the background; for the layer's texels the
-    bilinear weights sum to 1, so the texel sums total (1, T_end, T_end bg, alpha_layer)."""
-    n, step = 8, 0.6
-    spec = ps.SceneSpec(n, n, n, layer_radii=(1.8,), env_w=16, env_h=8, step_vox=step,
-                        background=(0.3, 0.6, 0.05))
-    h = 2.0 / n
-    cams = ps.cameras_from_origins([[3.0, 0.0, 0.0]], 1, 1, 20.0)
-    cams.origin[0] = [3.0, -1 + 2.5 * h, -1 + 5.5 * h]
-    cams.rot[0] = np.array([[0.0, 0.0, -1.0], [1.0, 0.0, 0.0], [0.0, -1.0, 0.0]])
-    sigma, c0 = 0.35, np.array([0.2, 0.5, 0.9])
-    ce, ae = np.array([0.7, 0.1, 0.4]), 0.8
-    grid = np.zeros((n, n, n, 4)); grid[..., :3] = c0; grid[..., 3] = sigma
-    env = np.zeros((1, spec.env_h, spec.env_w, 4)); env[..., :3] = ce; env[..., 3] = ae
-    x = np.concatenate([grid.reshape(-1), env.reshape(-1)])
-    sc = oracle_mod.OracleScene(spec, cams)
-    sums = sc.feature_sums(x)
-    # closed form (the step as the scene holds it, a single-precision value)
-    step = spec.step_vox
-    L = 2.0 / h
-    K = int(np.ceil(L / step))
-    delta = np.minimum(step, L - step * np.arange(K))
-    s_mid = step * np.arange(K) + 0.5 * delta          # voxel lengths from the entry at x = +1
-    gx = np.clip(7.5 - s_mid, 0.0, n - 1.0)            # cell-centred grid coordinate along x
-    alpha = 1.0 - np.exp(-sigma * delta)
-    T = np.exp(-sigma * np.concatenate([[0.0], np.cumsum(delta)[:-1]]))
-    T_end = np.exp(-sigma * delta.sum())
-    S = ae * ce + (1 - ae) * np.array(spec.background)
-    G = np.array([(T[k + 1:] * alpha[k + 1:]).sum() * c0 + T_end * S for k in range(K)])
-    want = np.zeros((n, 6))
-    for i in range(n):
-        wgt = np.maximum(0.0, 1.0 - np.abs(gx - i))
-        want[i] = [wgt.sum(), (wgt * T).sum(), *(wgt[:, None] * G).sum(0), (wgt * alpha).sum()]
-    vox = sums[:spec.n_vox].reshape(n, n, n, 6)
-    np.testing.assert_allclose(vox[5, 2, :], want, rtol=1e-12, atol=1e-15)
-    mask = np.ones((n, n, n), bool); mask[5, 2, :] = False
-    assert np.all(vox[mask] == 0.0)
-    tex = sums[spec.n_vox:].sum(0)
-    np.testing.assert_allclose(tex, [1.0, T_end, *(T_end * np.array(spec.background)), ae], rtol=1e-12)
-
-
 def test_feature_stats_closed_form(mlp):
     """Column i = a_i + b_i t with t = +-1 alternating: mean a_i, population std |b_i|; a
     constant column gets s = 1 / 1e-3; the padding stays 0."""
-    a = np.linspace(-20.0, 5.0, 12)
-    b = np.linspace(0.5, 3.0, 12)
-    b[7] = 0.0
+    a = np.linspace(-20.0, 5.0, 6)
+    b = np.linspace(0.5, 3.0, 6)
+    b[4] = 0.0
     t = np.tile([1.0, -1.0], 50)
     feat = a[None, :] + b[None, :] * t[:, None]
     norm = mlp.feature_stats(feat)
-    np.testing.assert_allclose(norm[:12], a, rtol=1e-14, atol=1e-13)
+    np.testing.assert_allclose(norm[:6], a, rtol=1e-14, atol=1e-13)
     want = 1.0 / np.maximum(np.abs(b), 1e-3)
-    np.testing.assert_allclose(norm[16:28], want, rtol=1e-12)
-    assert np.all(norm[12:16] == 0) and np.all(norm[28:32] == 0)
+    np.testing.assert_allclose(norm[16:22], want, rtol=1e-12)
+    assert np.all(norm[6:16] == 0) and np.all(norm[22:32] == 0)
 
 
 def test_standardise_centres_scales_and_clamps(mlp):
     rng = np.random.default_rng(3)
-    feat = rng.normal(size=(200, 12)) * 4.0 + 10.0
+    feat = rng.normal(size=(200, 6)) * 4.0 + 10.0
     norm = mlp.feature_stats(feat)
     x = mlp.standardise(norm, feat)
-    inner = np.abs(x[:, :12]) < mlp.CLAMP
+    inner = np.abs(x[:, :6]) < mlp.CLAMP
     z = (feat - feat.mean(0)) / feat.std(0)
-    np.testing.assert_allclose(x[:, :12][inner], z[inner], rtol=1e-12)
+    np.testing.assert_allclose(x[:, :6][inner], z[inner], rtol=1e-12)
     far = feat.copy(); far[0, 3] = 1e6; far[1, 5] = -1e6
     xf = mlp.standardise(norm, far)
     assert xf[0, 3] == mlp.CLAMP and xf[1, 5] == -mlp.CLAMP
-    assert np.all(x[:, 12:] == 0)
+    assert np.all(x[:, 6:] == 0)
 
 
 def test_fallback_units_take_the_exact_block_inverse(mlp, oracle_mod):
@@ -254,7 +190,7 @@ def test_fallback_units_take_the_exact_block_inverse(mlp, oracle_mod):
     rng = np.random.default_rng(11)
     w = mlp.init_weights(4) + 0.2 * rng.normal(size=mlp.NW)
     blocks = random_blocks(60, 5)
-    feat = rng.normal(size=(60, 12))
+    feat = rng.normal(size=(60, mlp.N_IN))
     norm = unit_norm(mlp)
     M_all, fb_all, q = mlp.minv(w, norm, feat, blocks, q_fallback=0.0, return_fallback=True)
     np.testing.assert_allclose(M_all, oracle_mod.block_inverse(blocks), rtol=1e-9, atol=1e-12)
@@ -272,10 +208,10 @@ def test_fallback_units_take_the_exact_block_inverse(mlp, oracle_mod):
 
 
 def test_coupling_inputs_are_the_normalised_off_diagonal(mlp):
-    """Network inputs 12..14 are the block's colour-density coupling scaled to a unit diagonal:
+    """Network inputs 6..8 are the block's colour-density coupling scaled to a unit diagonal:
     for blocks built as e = rho sqrt(d f) u with a unit vector u, that is rho u up to the ridge
     (1e-6 max(d, f) added to d and f: at most 2.5e-5 relative here, d/f within 50); zero for units
-    no ray touches, and the last input slot stays zero."""
+    no ray touches, and the remaining input slots stay zero."""
     rng = np.random.default_rng(8)
     n = 50
     d = rng.uniform(0.1, 5.0, n)
@@ -285,8 +221,8 @@ def test_coupling_inputs_are_the_normalised_off_diagonal(mlp):
     rho = rng.uniform(0.0, 0.95, n)
     blocks = np.concatenate([d[:, None], u * (rho * np.sqrt(d * f))[:, None], f[:, None]], axis=1)
     blocks[:2] = 0.0
-    x = mlp.inputs(unit_norm(mlp), rng.normal(size=(n, 12)), blocks)
+    x = mlp.inputs(unit_norm(mlp), rng.normal(size=(n, mlp.N_IN)), blocks)
     want = u * rho[:, None]
-    np.testing.assert_allclose(x[2:, 12:15], want[2:], rtol=3e-5, atol=1e-12)
-    assert np.all(x[:2, 12:15] == 0) and np.all(x[:, 15] == 0)
-    assert np.all(np.linalg.norm(x[:, 12:15], axis=1) < 1.0)
+    np.testing.assert_allclose(x[2:, 6:9], want[2:], rtol=3e-5, atol=1e-12)
+    assert np.all(x[:2, 6:9] == 0) and np.all(x[:, 9:] == 0)
+    assert np.all(np.linalg.norm(x[:, 6:9], axis=1) < 1.0)

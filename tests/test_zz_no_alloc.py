@@ -12,7 +12,9 @@ torch = pytest.importorskip("torch")
 
 def _rows(n, seed):
     rng = np.random.default_rng(seed)
-    feat = rng.normal(size=(n, 12)) * rng.uniform(0.5, 3.0, 12) + rng.uniform(-5, 5, 12)
+    from paper_2112_05598_amd import abi
+    k = abi.PERF_MLP_NFEAT
+    feat = rng.normal(size=(n, k)) * rng.uniform(0.5, 3.0, k) + rng.uniform(-5, 5, k)
     d = rng.uniform(0.1, 5.0, n)
     f = rng.uniform(0.1, 5.0, n)
     dirs = rng.normal(size=(n, 3))
@@ -34,7 +36,7 @@ def test_noalloc_training_step_matches_the_buffered_one():
     st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
     rng = np.random.default_rng(3)
     w0 = mlp.init_weights(2) + 0.05 * rng.normal(size=mlp.NW)
-    p = mlp.unpack(w0); p["W1"][:, 12:] = 0; p["W3"][10:] = 0
+    p = mlp.unpack(w0); p["W1"][:, mlp.N_NET:] = 0; p["W3"][10:] = 0
     w0 = mlp.pack(p).astype(np.float32)
     state = {k: torch.from_numpy(w0.copy()).cuda() if k == "w32" else torch.zeros(mlp.NW, device="cuda")
              for k in ("w32", "m", "v")}
