@@ -21,6 +21,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -202,7 +203,8 @@ def main():
             "jacobi": {"gn_steps": args.steps, "pcg_iters": sum(s["pcg_iters"] for s in stats), "ms": dt * 1e3},
             "learned": {"gn_steps": run["gn_steps"], "pcg_iters": run["pcg_iters"], "ms": run["ms"],
                         "F": run["F"], "reached": run["F"][-1] <= F_target,
-                        "q_fallback": model.q_fallback, "fallback_frac_start_end": frac},
+                        "q_fallback": model.q_fallback if math.isfinite(model.q_fallback) else None,
+                        "fallback_frac_start_end": frac},
             "model": "paper_2112_05598_amd/weights/precond_mlp.npz"}
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a ray sample", file=sys.stderr, flush=True)
