@@ -172,14 +172,23 @@ def test_preconditioner_inverses(case):
 
 
 def test_footprint_counts(case):
+    """Distinct voxels per ray (the roofline's footprint) against the oracle's count: a sample that
+    sits on a cell boundary can fall on either side in FP32 and FP64, which moves one face of the
+    ray's corner boxes (at most 4 voxels); such rays are rare. Layer hits and rays in the grid are
+    exact, the total within 1e-4."""
     pr, tot = case.sc.footprint()
     pr = pr.cpu().numpy()
     U, L, K = case.orc.footprint()
-    agree = np.mean(pr[:, 0] == U)
-    assert agree >= 0.999
+    diff = pr[:, 0].astype(np.int64) - U
+    print(f"[footprint] {case.w.name}: {np.count_nonzero(diff)} of {len(U)} rays differ, "
+          f"max |diff| {np.abs(diff).max() if len(diff) else 0}, total {int(diff.sum())} of {int(U.sum())}",
+          flush=True)
+    assert np.count_nonzero(diff) <= 1e-3 * len(U)
+    assert np.all(np.abs(diff) <= 4)
     assert np.array_equal(pr[:, 1], L)
     t = tot.cpu().numpy()
-    assert abs(int(t[0]) - int(U.sum())) <= 1e-3 * U.sum() + 8
+    assert int(t[0]) == int(pr[:, 0].sum())
+    assert abs(int(t[0]) - int(U.sum())) <= 1e-4 * U.sum()
     assert int(t[1]) == int(L.sum()) and int(t[2]) == int((K > 0).sum())
 
 
