@@ -14,7 +14,9 @@ part of the step counts as overhead).  The roofline object prices the J^T J v ke
 alone: footprint bytes per launch (48 B per distinct voxel a ray touches + 192 B per
 environment layer it hits, 40 B and 160 B with bf16 parameter storage, counted exactly by
 the library's footprint pass) over the
-kernel's average duration measured with HIP events on the launch stream.
+kernel's average duration measured with HIP events on the launch stream.  Beside it,
+counted_hbm_gbs is the HBM traffic rocprofv3 counted for the same kernel source
+(profiles/jtj_cfg2_traffic.json) over the same duration: what actually crosses HBM.
 """
 from __future__ import annotations
 
@@ -174,8 +176,9 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_ray<M_JTJ> (J^T J v)", "avg_launch_ms": jtj_ms,
-                     "bytes_per_launch": bytes_per_launch, "launches": n_jtj,
-                     "kernel_rays_per_s": sc.n_rays / (jtj_ms * 1e-3)},
+                     "bytes_per_launch": bytes_per_launch, "achieved_basis": "footprint (algorithmic) bytes",
+                     "counted_hbm_gbs": None if traffic is None else traffic / (jtj_ms * 1e-3) / 1e9,
+                     "launches": n_jtj, "kernel_rays_per_s": sc.n_rays / (jtj_ms * 1e-3)},
         "gn": {"F": [stats[0]["F_before"]] + [s["F_after"] for s in stats],
                "ms_per_gn_step": [s["ms_phase"][5] for s in stats],
                "pcg_iters": [s["pcg_iters"] for s in stats], "gamma": [s["gamma"] for s in stats]},
