@@ -1,4 +1,4 @@
-"""GPU parity of the learned block preconditioner: feature pass, MFMA inference and the
+"""GPU parity of the learned block preconditioner: features, MFMA inference and the
 training kernel against the FP64 reference."""
 import numpy as np
 import pytest
