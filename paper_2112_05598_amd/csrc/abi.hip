@@ -516,10 +516,11 @@ int32_t perf_mlp_training_rows(perf_scene* s, const float* d_feat, const float* 
     return PERF_OK;
 }
 
-// features at x from the blocks of this step's gradient pass (in s->blocks) and the predicted
+// features from the parameters the gradient pass gathered (xg: the bfloat16 copy with bf16
+// storage, as perf_precond_features sees them) and its blocks (in s->blocks), then the predicted
 // inverses: no further traversal
-static int32_t learned_minv(perf_scene* s, const float* x32) {
-    CK(launch_unit_features(x32, PERF_F32, s->blocks, s->units, s->feat, s->stream));
+static int32_t learned_minv(perf_scene* s, const void* xg) {
+    CK(launch_unit_features(xg, s->desc.param_dtype, s->blocks, s->units, s->feat, s->stream));
     CK(launch_mlp_infer(s->mlpw, s->mlpnorm, s->q_fallback, s->feat, s->blocks, s->units, s->minv, s->stream));
     return PERF_OK;
 }
@@ -686,7 +687,7 @@ int32_t perf_gn_step(perf_scene* s, float* d_x, const perf_pcg_opts* opts, perf_
     if (kind == PERF_PRECOND_JACOBI || kind == PERF_PRECOND_BLOCK4) {
         CK(launch_precond_invert(kind, s->blocks, s->units, s->minv, st));
     } else if (kind == PERF_PRECOND_LEARNED) {
-        rc = learned_minv(s, d_x);
+        rc = learned_minv(s, xg);
         if (rc != PERF_OK) return rc;
         // keep b for a fallback solve: the feature rows (at least P floats) are free now
         CK(hipMemcpyAsync(s->feat, s->vr, sizeof(float) * s->P, hipMemcpyDeviceToDevice, st));

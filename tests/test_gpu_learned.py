@@ -279,3 +279,37 @@ def test_fallback_units_take_the_exact_block_inverse(setup):
     clear_lo = live & (q < 0.95 * thr)
     assert clear_hi.sum() > 10 and clear_lo.sum() > 10
     assert np.all(out[clear_hi, 0] < 0) and np.all(out[clear_lo, 0] > 0)
+
+
+def test_learned_gn_step_bf16_storage_matches_oracle():
+    """With bf16 parameter storage the learned GN step takes its features from the parameters the
+    gradient pass gathered (the bf16 copy), as perf_precond_features does for the same scene: its
+    PCG scalars match the oracle's GN step at the bf16-rounded parameters, run with the library's
+    own predicted inverse, to the J^T J v bound (1e-4), and the step lowers F."""
+    import oracle
+    from oracle import mlp
+    from gpu_checks import check_pcg_history, learned_minv
+    from paper_2112_05598_amd.scene import Scene
+    w = ps.workload("tiny")
+    print("[case] learned GN step, bf16 storage, tiny", flush=True)
+    orc = oracle.OracleScene(w.spec, w.cams)
+    targets = orc.render(w.x_gt)[0].astype(np.float32)
+    rng = np.random.default_rng(4)
+    x = w.x_init.copy().reshape(-1, 4)
+    x[:, 3] += rng.uniform(0, 0.5, x.shape[0]).astype(np.float32)
+    x = x.reshape(-1).astype(np.float32)
+    sc = Scene(w.spec, w.cams, torch.from_numpy(targets.reshape(-1)).cuda(), param_dtype="bf16", learned=True,
+               device="cuda:0")
+    tx = torch.from_numpy(x).cuda()
+    feat, blocks = sc.features(sc.pack_bf16(tx))
+    norm, _ = gpu_norm(feat)
+    bits, _ = learned_weights(7)
+    sc.mlp_set_weights(torch.from_numpy(bits.view(np.int16)).cuda().view(torch.bfloat16), norm)
+    minv_gpu = learned_minv(sc.mlp_infer(feat, blocks).cpu().numpy())
+    st = sc.gn_step(tx.clone(), max_iters=8, precond="learned")
+    assert st["F_after"] < st["F_before"] and st["fallback_iters"] == 0
+    xb = mlp.bf16_round(x).astype(np.float64)
+    ref = oracle.gn_step(orc, xb, targets, precond="learned", max_iters=8, learned_minv=minv_gpu)
+    assert abs(st["F_before"] - ref["F_before"]) <= 1e-5 * ref["F_before"]
+    assert st["pcg_iters"] == ref["pcg"].iters
+    check_pcg_history(st, ref["pcg"], min(5, ref["pcg"].iters), tol=1e-4)
