@@ -276,7 +276,7 @@ int32_t perf_invert_blocks(const float* d_blocks, int64_t units, int32_t kind, f
 int32_t perf_pack_bf16(const float* d_in, uint16_t* d_out, int64_t n, void* stream);
 
 /*
- * Learned block preconditioner (per-unit MLP 9 -> 64 -> 64 -> 10, ReLU, BF16 weights on
+ * Learned block preconditioner (per-unit MLP 10 -> 64 -> 64 -> 10, ReLU, BF16 weights on
  * MFMA, FP32 accumulation).  Not in the paper: it replaces the exact 4x4 block inverse of
  * Sec. III-G's diagonal preconditioner by a prediction from cheap per-unit features.
  *
@@ -284,12 +284,14 @@ int32_t perf_pack_bf16(const float* d_in, uint16_t* d_out, int64_t n, void* stre
  *   (as in perf_build_precond) from the gradient/block traversal at x; the features come from
  *   x and the blocks alone (no further traversal): sigma/alpha, colour (3), log(d + 1e-12),
  *   log(f + 1e-12).  perf_gn_step forms them from the blocks of its own gradient pass.
- * The network's input (9 values, padded to 16) is the standardised feature vector
+ * The network's input (10 values, padded to 16) is the standardised feature vector
  *   clamp((f - mu) s, -8, 8), with norm [PERF_MLP_NNORM] = (mu[16], s[16]) FP32 (entries 6..15
  *   of each zero), followed by the unit's normalised colour-density coupling e~ = e /
- *   sqrt((d + rho)(f + rho)) from d_blocks (|e~| < 1, not standardised; 0 for an empty unit).
+ *   sqrt((d + rho)(f + rho)) from d_blocks (|e~| < 1) and -1/2 log(1 - |e~|^2), the log of
+ *   1 / sqrt of the normalised block's Schur complement (8 where the complement is at most
+ *   exp(-16)); neither is standardised, and all are 0 for an empty unit.
  * perf_mlp_set_weights: d_w device bfloat16 weights in the packed order W1[64][16] b1[64]
- *   W2[64][64] b2[64] W3[16][64] b3[16] (inputs padded 9 -> 16, outputs 10 -> 16 with zeros);
+ *   W2[64][64] b2[64] W3[16][64] b3[16] (inputs padded 10 -> 16, outputs 10 -> 16 with zeros);
  *   n_w must equal PERF_MLP_NW; d_norm the network's standardisation (device FP32); q_fallback:
  *   a unit whose prediction misses its own normalised block B~ by q = ||L L^T B~ - I||_F^2 >
  *   q_fallback takes the exact block inverse instead (plain block-Jacobi as the fallback;

@@ -7,12 +7,14 @@ per-unit features.  Conventions, identical to the product's:
   features:        6 per unit, from x and the unit's block alone: sigma/alpha, colour (3),
                    log d, log f
   weights, packed: W1[64][16] b1[64] W2[64][64] b2[64] W3[16][64] b3[16]
-                   (inputs padded 9 -> 16, outputs 10 -> 16 with zeros)
+                   (inputs padded 10 -> 16, outputs 10 -> 16 with zeros)
   standardisation: norm = (mu[16], s[16]) from the training features: mu the mean and
                    s = 1 / max(std, 1e-3) per feature (0 for the other slots)
   inputs:          x[0:6] = clamp((feature - mu) s, -CLAMP, CLAMP) for the 6 features,
                    x[6:9] = e~, the normalised colour-density coupling of the unit's block
-                   (the off-diagonal column of B~ below; |e~| < 1, used as is), x[9:16] = 0
+                   (the off-diagonal column of B~ below; |e~| < 1, used as is),
+                   x[9] = -1/2 log(1 - |e~|^2) (the Schur complement's log; 8 where the
+                   complement is at most exp(-16)), x[10:16] = 0
   network:         h1 = relu(W1 x + b1), h2 = relu(W2 h1 + b2), o = W3 h2 + b3
   factor:          L lower triangular from o[0:10] row by row, softplus on the diagonal
   ridge:           rho = 1e-6 max(d, f); D = diag(d, d, d, f) + rho I
@@ -30,8 +32,9 @@ from __future__ import annotations
 import numpy as np
 
 N_IN, N_IN_PAD, N_HID, N_OUT, N_OUT_PAD = 6, 16, 64, 10, 16
-N_CPL = 3               # network inputs taken from the block: the normalised coupling e~
+N_CPL = 4               # network inputs taken from the block: e~ (3) and its Schur log
 N_NET = N_IN + N_CPL    # network inputs in use
+SCHUR_CAP = 8.0         # cap on the Schur log input
 SHAPES = [("W1", (N_HID, N_IN_PAD)), ("b1", (N_HID,)), ("W2", (N_HID, N_HID)), ("b2", (N_HID,)),
           ("W3", (N_OUT_PAD, N_HID)), ("b3", (N_OUT_PAD,))]
 NW = sum(int(np.prod(s)) for _, s in SHAPES)
@@ -123,11 +126,17 @@ def standardise(norm: np.ndarray, feat: np.ndarray) -> np.ndarray:
 
 
 def inputs(norm: np.ndarray, feat: np.ndarray, blocks: np.ndarray) -> np.ndarray:
-    """[n, 16] network inputs: the standardised stored features, then e~ of each unit's block
-    (zero for a unit with no rays or a non-finite block), then one zero."""
+    """[n, 16] network inputs: the standardised stored features, then e~ of each unit's block and
+    -1/2 log(s) with s = 1 - |e~|^2 the Schur complement of B~ (the inverse's entries grow as 1/s),
+    SCHUR_CAP where s <= exp(-2 SCHUR_CAP); all zero for a unit with no rays or a non-finite block;
+    then zeros."""
     x = standardise(norm, feat)
-    Bn, _, _ = normalised_block(blocks)
-    x[:, N_IN:N_NET] = Bn[:, 0:3, 3]
+    Bn, _, live = normalised_block(blocks)
+    e = Bn[:, 0:3, 3]
+    x[:, N_IN:N_IN + 3] = e
+    s = 1.0 - (e * e).sum(axis=1)
+    ok = live & (s > np.exp(-2.0 * SCHUR_CAP))  # else the cap (also for a block that rounding left indefinite)
+    x[:, N_IN + 3] = np.where(ok, -0.5 * np.log(np.where(ok, s, 1.0)), np.where(live, SCHUR_CAP, 0.0))
     return x
 
 

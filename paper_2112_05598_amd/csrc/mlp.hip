@@ -1,4 +1,4 @@
-// Learned block preconditioner on gfx950: per-unit MLP 9 -> 64 -> 64 -> 10 with bfloat16
+// Learned block preconditioner on gfx950: per-unit MLP 10 -> 64 -> 64 -> 10 with bfloat16
 // operands on the matrix cores (v_mfma_f32_32x32x8_bf16) and FP32 accumulation.
 //
 // Not part of the paper: Sec. III-G preconditions PCG with the diagonal of J^T J; here the
@@ -10,7 +10,8 @@
 //
 // The network's input is the standardised feature vector clamp((f - mu) s, -8, 8), with mu and
 // s = 1 / max(std, 1e-3) taken from the training set (norm [32] = mu[16], s[16]), followed by
-// the normalised colour-density coupling e~ of the unit's block (three values in (-1, 1)).  At inference
+// the normalised colour-density coupling e~ of the unit's block (three values in (-1, 1)) and the
+// log of 1 / sqrt of its Schur complement.  At inference
 // a unit whose prediction misses its own normalised block by q = ||L L^T B~ - I||_F^2 above a
 // threshold takes the exact block inverse instead (plain block-Jacobi as the fallback).
 //
@@ -33,7 +34,8 @@ typedef float f16v __attribute__((ext_vector_type(16)));
 typedef LDS unsigned short lds_bf;
 
 constexpr int NIN = PERF_MLP_NFEAT, NIP = 16, NH = 64, NO = 10, NOP = 16;
-constexpr int NNET = NIN + 3;  // network inputs: the stored features, then the block's normalised coupling
+constexpr int NNET = NIN + 4;  // network inputs: the stored features, the block's coupling and its Schur log
+constexpr float kSchurCap = 8.0f;  // cap on the Schur log input
 constexpr int OFF_W1 = 0, OFF_B1 = OFF_W1 + NH * NIP, OFF_W2 = OFF_B1 + NH, OFF_B2 = OFF_W2 + NH * NH,
               OFF_W3 = OFF_B2 + NH, OFF_B3 = OFF_W3 + NOP * NH, NW = OFF_B3 + NOP;
 static_assert(NW == PERF_MLP_NW, "packed weight layout");
@@ -182,32 +184,42 @@ __device__ __forceinline__ void make_L(const float raw[NO], float L[4][4]) {
 }
 
 // standardised features of one unit into the X tile row (bf16, zero padded): clamp((f - mu) s)
-// The normalised colour-density coupling e~ = e / sqrt((d + rho)(f + rho)) of a unit's block
-// [d, e (3), f] (|e~| < 1 for a positive semi-definite block); zero for a unit no ray touches or
-// a non-finite block.  In double: d may be subnormal.
-__device__ __forceinline__ void block_coupling(const float* __restrict__ b, float e[3]) {
+// The block inputs of a unit's block [d, e (3), f]: the normalised colour-density coupling
+// e~ = e / sqrt((d + rho)(f + rho)) (|e~| < 1 for a positive semi-definite block), then
+// -1/2 log(1 - |e~|^2), the log of 1 / sqrt of the Schur complement of the normalised block (the
+// inverse's entries grow as its inverse), 8 where the complement is at most exp(-16).  All zero
+// for a unit no ray touches or a non-finite block.  In double: d may be subnormal, and
+// 1 - |e~|^2 cancels.
+__device__ __forceinline__ void block_inputs(const float* __restrict__ b, float e[4]) {
     const float d = b[0], f = b[4];
     const float m = fmaxf(d, f);
     bool finite = true;
 #pragma unroll
     for (int i = 0; i < 5; ++i) finite &= isfinite(b[i]);
     if (!(m > 0.0f) || !finite) {
-        e[0] = e[1] = e[2] = 0.0f;
+        e[0] = e[1] = e[2] = e[3] = 0.0f;
         return;
     }
     const double rho = (double)kRidge * m;
     const double s = 1.0 / sqrt(((double)d + rho) * ((double)f + rho));
+    double n2 = 0.0;
 #pragma unroll
-    for (int i = 0; i < 3; ++i) e[i] = (float)(b[1 + i] * s);
+    for (int i = 0; i < 3; ++i) {
+        const double ei = b[1 + i] * s;
+        e[i] = (float)ei;
+        n2 += ei * ei;
+    }
+    const double sc = 1.0 - n2;  // at most exp(-2 cap), or below zero where rounding left the block indefinite: the cap
+    e[3] = sc > exp(-2.0 * (double)kSchurCap) ? (float)(-0.5 * log(sc)) : kSchurCap;
 }
 
 // one unit's network inputs, rounded to bfloat16: its standardised stored features (clamped),
-// then the coupling of its block as is, then zeros
+// then the block inputs as they are, then zeros
 __device__ __forceinline__ void load_features(const float* __restrict__ feat, const float* __restrict__ norm,
                                               const float* __restrict__ blocks, int64_t unit, int64_t n,
                                               lds_bf* Xrow, lds_bf* Xt, int col) {
-    float cpl[3] = {0.0f, 0.0f, 0.0f};
-    if (unit < n) block_coupling(blocks + 5 * unit, cpl);
+    float cpl[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    if (unit < n) block_inputs(blocks + 5 * unit, cpl);
 #pragma unroll
     for (int i = 0; i < NIP; ++i) {
         float v = 0.0f;

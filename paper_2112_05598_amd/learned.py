@@ -37,7 +37,7 @@ class Model:
 def init_weights(seed: int = 0) -> np.ndarray:
     """He-style initialisation (float64, packed order); the network starts at L = I."""
     rng = np.random.default_rng(seed)
-    nh, ni, nip, no, nop = 64, 9, 16, 10, 16  # 6 features + the block's 3 couplings
+    nh, ni, nip, no, nop = 64, 10, 16, 10, 16  # 6 features + the block's coupling (3) and Schur log
     W1 = rng.normal(0, np.sqrt(2.0 / ni), (nh, nip)); W1[:, ni:] = 0.0
     W2 = rng.normal(0, np.sqrt(2.0 / nh), (nh, nh))
     W3 = np.zeros((nop, nh))  # start exactly at L = I: the Jacobi preconditioner

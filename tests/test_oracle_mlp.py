@@ -208,7 +208,8 @@ def test_fallback_units_take_the_exact_block_inverse(mlp, oracle_mod):
 
 
 def test_coupling_inputs_are_the_normalised_off_diagonal(mlp):
-    """Network inputs 6..8 are the block's colour-density coupling scaled to a unit diagonal:
+    """Network inputs 6..8 are the block's colour-density coupling scaled to a unit diagonal, input 9
+    the log of 1 / sqrt of the normalised block's Schur complement:
     for blocks built as e = rho sqrt(d f) u with a unit vector u, that is rho u up to the ridge
     (1e-6 max(d, f) added to d and f: at most 2.5e-5 relative here, d/f within 50); zero for units
     no ray touches, and the remaining input slots stay zero."""
@@ -224,5 +225,13 @@ def test_coupling_inputs_are_the_normalised_off_diagonal(mlp):
     x = mlp.inputs(unit_norm(mlp), rng.normal(size=(n, mlp.N_IN)), blocks)
     want = u * rho[:, None]
     np.testing.assert_allclose(x[2:, 6:9], want[2:], rtol=3e-5, atol=1e-12)
-    assert np.all(x[:2, 6:9] == 0) and np.all(x[:, 9:] == 0)
     assert np.all(np.linalg.norm(x[:, 6:9], axis=1) < 1.0)
+    # input 9: -1/2 log of the Schur complement 1 - rho^2 of the normalised block (the ridge moves
+    # |e~|^2 by at most 5e-5 relative, 1 - rho^2 >= 0.0975 here)
+    np.testing.assert_allclose(x[2:, 9], -0.5 * np.log1p(-rho[2:] ** 2), rtol=0, atol=1e-3)
+    assert np.all(x[:2, 6:10] == 0) and np.all(x[:, 10:] == 0)
+    # the ridge keeps a singular block's complement near 2e-6 (input about 6.6); a block that
+    # rounding left indefinite (|e~| > 1) takes the cap rather than the log of a negative number
+    sing = np.array([[1.0, 1.0, 0.0, 0.0, 1.0], [1.0, 1.5, 0.0, 0.0, 1.0]])
+    xs = mlp.inputs(unit_norm(mlp), np.zeros((2, mlp.N_IN)), sing)[:, 9]
+    assert abs(xs[0] + 0.5 * np.log(1.0 - 1.0 / (1.0 + 1e-6) ** 2)) < 1e-6 and xs[1] == mlp.SCHUR_CAP
