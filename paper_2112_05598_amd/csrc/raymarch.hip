@@ -461,16 +461,34 @@ struct Brick4 {
         win.o[0] = win.o[1] = win.o[2] = -(1 << 24);
         for (int i = lane_id(); i < kB3; i += 64) s[i] = f4{0.0f, 0.0f, 0.0f, 0.0f};
     }
+    // Flush one leaving voxel per lane (a uniform call: every lane holds one).  Where most voxels
+    // of the pass carry all four channels (a medium with some density everywhere), the adds go
+    // out four lanes per voxel, one channel each, so a voxel's four adds form one 16-byte run and
+    // the L2 sees about a quarter of the atomic requests; where most carry only the sigma channel
+    // (empty space: alpha = 0 zeroes the colour channels), each lane sends its own nonzero channels.
     template <class Sink>
     __device__ __forceinline__ void flush_voxel(const Geo& G, int x, int y, int z, Sink& out) {
         const int sl = ring_slot(x, y, z);
         const f4 v = s[sl];
-        s[sl] = f4{0.0f, 0.0f, 0.0f, 0.0f};
-        if ((v.x != 0.0f || v.y != 0.0f || v.z != 0.0f || v.w != 0.0f) && x >= 0 && y >= 0 && z >= 0 &&
-            x < G.nx && y < G.ny && z < G.nz) {
+        const bool in = x >= 0 && y >= 0 && z >= 0 && x < G.nx && y < G.ny && z < G.nz;
+        const int u = (z * G.ny + y) * G.nx + x;
+        const bool full = in && v.x != 0.0f && v.y != 0.0f && v.z != 0.0f && v.w != 0.0f;
+        if (__popcll(__ballot(full)) >= 32) {
+            const int ch = lane_id() & 3;
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                const int j = g * 16 + (lane_id() >> 2);
+                const int uj = __shfl(u, j, 64);
+                const int slj = __shfl(sl, j, 64);
+                const int inj = __shfl(in ? 1 : 0, j, 64);
+                const float f = ((volatile lds_float*)s)[4 * slj + ch];
+                if (inj && f != 0.0f) out.one(uj, ch, f);
+            }
+        } else if (in && (v.x != 0.0f || v.y != 0.0f || v.z != 0.0f || v.w != 0.0f)) {
             const float vv[4] = {v.x, v.y, v.z, v.w};
-            out((z * G.ny + y) * G.nx + x, vv);
+            out(u, vv);
         }
+        s[sl] = f4{0.0f, 0.0f, 0.0f, 0.0f};
     }
     __device__ __forceinline__ void clear_head(int n) {
         for (int i = lane_id(); i < n; i += 64) s[i] = f4{0.0f, 0.0f, 0.0f, 0.0f};
@@ -680,6 +698,7 @@ struct SinkY {  // y[4u + c], c < 4
         for (int c = 0; c < 4; ++c)
             if (v[c] != 0.0f) atomic_add(p + c, v[c]);
     }
+    __device__ __forceinline__ void one(int u, int c, float v) const { atomic_add(y + 4 * (size_t)u + c, v); }
 };
 struct SinkGrad {  // grad[4u + c] (c < 4) and blocks[5u + c] (channels 4..8)
     float* grad;
