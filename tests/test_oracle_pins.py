@@ -560,6 +560,30 @@ def test_gauss_newton_converges_near_ground_truth(oracle_mod):
     assert Fs[-1] < 1e-6 * Fs[0], Fs
 
 
+def test_learned_gn_step_falls_back_to_the_block_solve(oracle_mod):
+    """The learned GN step's failure rule (a reading of this library, not the paper): a learned
+    solve that stalls is replaced by the exact block-Jacobi solve from Delta_0 = 0, so the step
+    then equals the block step; without a failure the learned solve stands.  The learned M^-1
+    here is the exact block inverse scaled by 1/2 (a valid SPD preconditioner)."""
+    spec, sc, x_gt, targets = _observed_problem(oracle_mod)
+    rng = np.random.default_rng(3)
+    x = oracle_mod.project(spec, x_gt + 0.05 * rng.normal(size=x_gt.size))
+    _, blocks, _ = sc.grad_blocks(x, targets)
+    half = 0.5 * oracle_mod.block_inverse(blocks)
+    opts = dict(max_iters=6, stall_ratio=1e-12)
+    lrn = oracle_mod.gn_step(sc, x, targets, precond="learned", learned_minv=half, **opts)
+    blk = oracle_mod.gn_step(sc, x, targets, precond="block", **opts)
+    assert lrn["fallback_iters"] == 1 and "stall" in lrn["pcg"].flags
+    # (the oracle's threaded sums are not bitwise repeatable: 1e-9)
+    np.testing.assert_allclose(lrn["delta"], blk["delta"], rtol=1e-9, atol=1e-12 * np.abs(blk["delta"]).max())
+    assert lrn["gamma"] == blk["gamma"] and abs(lrn["F_after"] - blk["F_after"]) <= 1e-9 * blk["F_after"]
+    ok = oracle_mod.gn_step(sc, x, targets, precond="learned", learned_minv=half, max_iters=6)
+    assert ok["fallback_iters"] is None and ok["F_after"] < ok["F_before"]
+    # M^-1 / 2 and M^-1 give the same CG iterates up to the scaling of z: the same step
+    ref = oracle_mod.gn_step(sc, x, targets, precond="block", max_iters=6)
+    np.testing.assert_allclose(ok["delta"], ref["delta"], rtol=1e-9, atol=1e-12 * np.abs(ref["delta"]).max())
+
+
 # ------------------------------------------------------------------ hierarchy (Sec. IV)
 
 def _half_spec(spec):
